@@ -1,0 +1,194 @@
+/*
+ * gpnufft — MI355X (gfx950) library for Gaussian-process regression with the
+ * non-stationary isotropic Matern kernel, following Kielstra & Lindsey,
+ * "Gaussian process regression with log-linear scaling for common
+ * non-stationary kernels" (arXiv 2407.03608).
+ *
+ * The library applies the approximate kernel matrix K~ of eq:Ktilde (section
+ * 3.5) by the five-step algorithm of section 4.2 (type-1 NUFFT, pointwise
+ * Fourier mixing, type-2 NUFFT) and solves (K~ + eta^2 I) alpha = y
+ * (eq:gprsolve) by conjugate gradients (section 1, section 6.2).
+ *
+ * Kernel, in the caller's parameterisation:
+ *   K(x,y) = s(x) s(y) [2 l(x) l(y) / (l(x)^2 + l(y)^2)]^(d/2)
+ *            * phi_nu(|x - y| sqrt(2 / (l(x)^2 + l(y)^2)))
+ * with vertical scale s(x) > 0, length scale l(x) > 0 and phi_nu the Matern
+ * function of eq:matern (phi(0) = 1); nu = +INFINITY is the squared
+ * exponential eq:squaredexp.  This is eq:nonstat2 with sigma_p(x) = l(x)/sqrt(2)
+ * and w(x) = s(x) (sqrt(2 pi) l(x))^(d/2), so K(x,x) = s(x)^2.
+ *
+ * Conventions for every entry point:
+ *  - Return value 0 (GP_OK) or a negative GP_E* code; on error the message
+ *    is available from gp_last_error() (thread-local) and outputs are left
+ *    untouched unless stated otherwise.  No C++ exception crosses the ABI.
+ *  - All array arguments are fp64 DEVICE pointers (HBM), in the caller's
+ *    point order.  Points are row-major n x d.
+ *  - Work is ordered on the plan's HIP stream (gp_opts.stream, default the
+ *    null stream); entry points that return host-visible results
+ *    (gp_cg_solve's info) synchronise that stream.
+ *  - A plan copies what it needs at creation and keeps no reference to the
+ *    caller's buffers.  One thread may use a plan at a time; distinct plans
+ *    are independent and may be used concurrently on distinct streams.
+ */
+#ifndef GPNUFFT_H
+#define GPNUFFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+#define GP_OK 0
+#define GP_EINVAL (-1)      /* bad argument (null pointer, d not in 1..3, n < 1, ...) */
+#define GP_EDOMAIN (-2)     /* s <= 0, l <= 0, nu <= 0, eta < 0, tol <= 0 or non-finite input */
+#define GP_ERANGE (-3)      /* posterior target outside the plan's box or length-scale range */
+#define GP_ENOMEM (-4)      /* device allocation failed or exceeds gp_opts.max_device_bytes */
+#define GP_ENOCONV (-5)     /* CG hit max_iter; alpha holds the last iterate, info is filled */
+#define GP_EDEVICE (-6)     /* HIP runtime error */
+#define GP_EUNSUPPORTED (-7) /* parameters outside what the kernels support (e.g. n_f too large) */
+
+/* --------------------------------------------------------------- precision */
+#define GP_FP64 0           /* spread / FFT / mix / interpolate in fp64 */
+#define GP_FP32_BULK 1      /* spread / FFT / mix / interpolate in fp32; fp64 vectors and dots */
+
+typedef struct gp_plan_s* gp_plan_t;
+
+/* Plan options.  Initialise with gp_opts_init(); every field then means
+ * "choose automatically" until set.  The approximation parameters are those
+ * of section 3.5 (t_min, t_max, N_t, N_sigma, M, Delta-omega); setting them
+ * reproduces an exact operator K~ (for example to compare with a reference). */
+typedef struct {
+  int precision;            /* GP_FP64 (default) or GP_FP32_BULK */
+  double nufft_tol;         /* spreading tolerance; 0 = tol (fp64) or max(tol, 1e-6) (fp32) */
+  int n_sigma;              /* Chebyshev degree N_sigma (eq:chebscheme); -1 = auto */
+  int n_t;                  /* trapezoid intervals N_t (eq:dtscheme); -1 = auto; ignored for SE */
+  double t_min, t_max;      /* t range; used only when n_t >= 1 is set */
+  double dw;                /* Fourier spacing Delta-omega (section 3.4); 0 = auto */
+  int64_t M;                /* Fourier half-width M (grid {-M..M}^d); 0 = auto */
+  int64_t M_cap;            /* upper bound for automatic M; 0 = library default */
+  double s_min, s_max;      /* width range [sigma_min, sigma_max] in mapped units; 0 = from data */
+  int use_box;              /* 1: map the box [box_lo, box_hi] (not the data's) onto [-1,1]^d */
+  double box_lo[3], box_hi[3];
+  double l_lo, l_hi;        /* widen the length-scale range (posterior targets); 0 = unused */
+  size_t max_device_bytes;  /* admission limit for the plan's device memory; 0 = none */
+  void* stream;             /* hipStream_t; NULL = null stream */
+} gp_opts;
+
+/* What the plan chose (all in the mapped coordinates x' = (x - center) * scale). */
+typedef struct {
+  int d;
+  int64_t n;
+  int precision;
+  double nu, eta;
+  double t_min, t_max;
+  int n_t;                  /* N_t (0 for SE) */
+  double s_min, s_max;      /* sigma_min, sigma_max of eq:chebscheme */
+  int n_sigma;              /* N_sigma */
+  double dw;                /* Delta-omega */
+  int64_t M;                /* Fourier grid {-M..M}^d */
+  double center[3];
+  double scale;             /* x' = (x - center) * scale, l' = l * scale */
+  int nf[3];                /* oversampled FFT length per dimension */
+  int w;                    /* spreading window width (cells) */
+  double beta;              /* exponential-of-semicircle shape parameter */
+  double nufft_tol;
+  int lo[3], na[3];         /* active sub-box of the fine grid (offset, length) */
+  int tile[3];              /* spreading tile per dimension */
+  int n_pairs;              /* complex grids; each packs two real grids */
+  size_t device_bytes;      /* device memory held by the plan */
+  double pred_tail;         /* predicted spectral-tail error of the Fourier box, relative */
+  int m_capped;             /* 1 if M was limited by M_cap */
+} gp_plan_params;
+
+typedef struct {
+  int iters;                /* CG iterations taken (all refinement passes) */
+  int status;               /* GP_OK or GP_ENOCONV */
+  double rel_res;           /* recursive ||r||/||y|| at exit */
+  double rel_res_true;      /* refined solve: true residual with the outer operator; plain CG: -1 (use gp_residual) */
+  double seconds;           /* wall time of the solve */
+  int refinements;          /* outer refinement passes (gp_cg_solve_refined) */
+} gp_cg_info;
+
+/* Fill opts with "automatic" for every field.  Always returns GP_OK. */
+int gp_opts_init(gp_opts* opts);
+
+/* Build a plan for the kernel of this header on n points in d = 1..3
+ * dimensions (eq:boldK).  pts (n x d), sigma (n), l (n): device fp64.
+ * nu > 0 (INFINITY = squared exponential), eta >= 0 noise s.d. (eq:gprsolve),
+ * tol > 0 target accuracy for the approximation (section 5 / section 6).
+ * Parameter choices: see gp_plan_params and the design notes.  On success
+ * *out owns all device memory it needs; release it with gp_plan_destroy. */
+int gp_plan(int d, int64_t n, const double* pts, const double* sigma, const double* l,
+            double nu, double eta, double tol, const gp_opts* opts, gp_plan_t* out);
+
+/* Device bytes a plan with these arguments would hold (admission control).
+ * Same arguments as gp_plan; reads the points to size the grids. */
+int gp_plan_query(int d, int64_t n, const double* pts, const double* sigma, const double* l,
+                  double nu, double eta, double tol, const gp_opts* opts, size_t* bytes);
+
+int gp_plan_info(gp_plan_t plan, gp_plan_params* out);
+
+/* out = K~ alpha (add_noise = 0) or (K~ + eta^2 I) alpha (add_noise = 1):
+ * the five steps of section 4.2.  alpha, out: device fp64, length n, caller
+ * order; may not alias. */
+int gp_matvec(gp_plan_t plan, const double* alpha, double* out, int add_noise);
+
+/* Conjugate gradients on (K~ + eta^2 I) alpha = y (eq:gprsolve), unpreconditioned
+ * as in section 6.2.  alpha: in = initial guess if use_x0, out = solution.
+ * Stops when the recursive residual ||r||/||y|| <= tol or after max_iter
+ * iterations (GP_ENOCONV, alpha = last iterate).  Vector arithmetic and dot
+ * products are fp64 in both precisions; the residual is recomputed from the
+ * operator every `replace_every` iterations (0 = never). */
+int gp_cg_solve(gp_plan_t plan, const double* y, double* alpha, int use_x0, double tol,
+                int max_iter, int replace_every, gp_cg_info* info);
+
+/* Mixed-precision solve: CG with the operator of `inner` (typically
+ * GP_FP32_BULK) inside fp64 iterative refinement with the operator of
+ * `outer` (GP_FP64) on the same points: x_0 = 0; r = y - A_outer x;
+ * solve A_inner d = r by CG to relative tolerance max(tol ||y||/||r||, inner_tol);
+ * x += d; repeat while ||r||/||y|| > tol, at most max_refine passes. */
+int gp_cg_solve_refined(gp_plan_t inner, gp_plan_t outer, const double* y, double* alpha,
+                        double tol, double inner_tol, int max_iter, int max_refine,
+                        int replace_every, gp_cg_info* info);
+
+/* Posterior mean eq:postmean, mu(x*) = sum_n alpha_n K~(x*, x_n), at m
+ * targets (m x d device fp64) with their own scales sigma_t, l_t.  Targets
+ * must lie inside the plan's box and length-scale range (GP_ERANGE
+ * otherwise; widen them at plan time with gp_opts.use_box / l_lo / l_hi). */
+int gp_posterior_mean(gp_plan_t plan, const double* alpha, int64_t m, const double* targets,
+                      const double* sigma_t, const double* l_t, double* mu);
+
+/* ||y - (K~ + eta^2 I) alpha|| / ||y|| with the plan's operator (the true
+ * residual of eq:gprsolve).  Synchronises the plan's stream. */
+int gp_residual(gp_plan_t plan, const double* y, const double* alpha, double* rel_res);
+
+/* Per-kernel device timing.  With timing on, every kernel group of the matvec
+ * and the CG vector update is bracketed by HIP events on the plan's stream;
+ * gp_plan_get_timing synchronises and returns, per phase, the number of
+ * launches and the summed event time.  gp_plan_set_timing(plan, 1) resets. */
+#define GP_TIMING_PHASES 10
+typedef struct {
+  int n_phases;
+  const char* name[GP_TIMING_PHASES];   /* spread, fft_fwd_0..2, mode, fft_inv_2..0, interp, cg_vec */
+  int64_t launches[GP_TIMING_PHASES];
+  double ms[GP_TIMING_PHASES];
+} gp_timing;
+int gp_plan_set_timing(gp_plan_t plan, int enable);
+int gp_plan_get_timing(gp_plan_t plan, gp_timing* out);
+
+/* Change the stream later work of this plan is ordered on. */
+int gp_plan_set_stream(gp_plan_t plan, void* stream);
+
+int gp_plan_destroy(gp_plan_t plan);
+
+/* Message of the last error on this thread ("" if none). */
+const char* gp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GPNUFFT_H */

@@ -1,0 +1,380 @@
+// C ABI of gpnufft (declarations and contracts in include/gpnufft.h).
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "gp_internal.h"
+
+namespace gp {
+namespace {
+thread_local std::string g_err;
+}
+void set_error(const std::string& m) { g_err = m; }
+void clear_error() { g_err.clear(); }
+
+__global__ void axpy_kernel(int64_t n, double a, const double* __restrict__ x, double* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] += a * x[i];
+}
+__global__ void sub_kernel(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
+                           double* __restrict__ c) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    c[i] = a[i] - b[i];
+}
+static unsigned blocks(int64_t n) { return (unsigned)std::min<int64_t>((n + 255) / 256, 4096); }
+
+const char* const kPhaseNames[PH_COUNT] = {"spread", "fft_fwd_0", "fft_fwd_1", "fft_fwd_2",
+                                           "mode",   "fft_inv_2", "fft_inv_1", "fft_inv_0",
+                                           "interp", "cg_vec"};
+
+static hipEvent_t take_event(Plan* P) {
+  if (!P->pool.empty()) {
+    hipEvent_t e = P->pool.back();
+    P->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  GP_HIP(hipEventCreate(&e));
+  return e;
+}
+
+PhaseScope::PhaseScope(Plan* p, int ph) : P(p), phase(ph) {
+  if (!P->timing) return;
+  b = take_event(P);
+  GP_HIP(hipEventRecord(b, P->stream));
+}
+
+PhaseScope::~PhaseScope() {
+  if (!P->timing || !b) return;
+  hipEvent_t e = nullptr;
+  if (!P->pool.empty()) {
+    e = P->pool.back();
+    P->pool.pop_back();
+  } else if (hipEventCreate(&e) != hipSuccess) {
+    return;
+  }
+  if (hipEventRecord(e, P->stream) != hipSuccess) return;
+  P->events.push_back(Plan::Ev{phase, b, e});
+}
+
+Plan::~Plan() {
+  for (auto& ev : events) {
+    (void)hipEventDestroy(ev.a);
+    (void)hipEventDestroy(ev.b);
+  }
+  for (auto e : pool) (void)hipEventDestroy(e);
+}
+}  // namespace gp
+
+using namespace gp;
+
+template <class F>
+static int guarded(F&& f) {
+  try {
+    clear_error();
+    return f();
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return GP_ENOMEM;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return GP_EDEVICE;
+  } catch (...) {
+    set_error("unknown error");
+    return GP_EDEVICE;
+  }
+}
+
+extern "C" {
+
+int gp_opts_init(gp_opts* o) {
+  if (!o) return GP_EINVAL;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = GP_FP64;
+  o->n_sigma = -1;
+  o->n_t = -1;
+  return GP_OK;
+}
+
+int gp_plan(int d, int64_t n, const double* pts, const double* sigma, const double* l, double nu,
+            double eta, double tol, const gp_opts* opts, gp_plan_t* out) {
+  return guarded([&] {
+    if (!out) throw Error{GP_EINVAL, "out is null"};
+    gp_plan_s* h = new gp_plan_s();
+    try {
+      build_plan(d, n, pts, sigma, l, nu, eta, tol, opts, &h->P, false, nullptr);
+    } catch (...) {
+      delete h;
+      throw;
+    }
+    *out = h;
+    return GP_OK;
+  });
+}
+
+int gp_plan_query(int d, int64_t n, const double* pts, const double* sigma, const double* l,
+                  double nu, double eta, double tol, const gp_opts* opts, size_t* bytes) {
+  return guarded([&] {
+    if (!bytes) throw Error{GP_EINVAL, "bytes is null"};
+    Plan P;
+    build_plan(d, n, pts, sigma, l, nu, eta, tol, opts, &P, true, bytes);
+    return GP_OK;
+  });
+}
+
+int gp_plan_info(gp_plan_t h, gp_plan_params* o) {
+  return guarded([&] {
+    if (!h || !o) throw Error{GP_EINVAL, "null argument"};
+    const Plan& P = h->P;
+    std::memset(o, 0, sizeof(*o));
+    o->d = P.d;
+    o->n = P.n;
+    o->precision = P.precision;
+    o->nu = P.nu;
+    o->eta = P.eta;
+    o->t_min = P.t_min;
+    o->t_max = P.t_max;
+    o->n_t = P.n_t;
+    o->s_min = P.s_min;
+    o->s_max = P.s_max;
+    o->n_sigma = P.n_sigma;
+    o->dw = P.dw;
+    o->M = P.M;
+    for (int r = 0; r < 3; ++r) {
+      o->center[r] = P.center[r];
+      o->nf[r] = P.nf[r];
+      o->lo[r] = P.lo[r];
+      o->na[r] = P.na[r];
+      o->tile[r] = P.tile[r];
+    }
+    o->scale = P.scale;
+    o->w = P.w;
+    o->beta = P.beta;
+    o->nufft_tol = P.nufft_tol;
+    o->n_pairs = P.npair;
+    o->device_bytes = P.device_bytes;
+    o->pred_tail = P.pred_tail;
+    o->m_capped = P.m_capped;
+    return GP_OK;
+  });
+}
+
+int gp_matvec(gp_plan_t h, const double* alpha, double* out, int add_noise) {
+  return guarded([&] {
+    if (!h || !alpha || !out) throw Error{GP_EINVAL, "null argument"};
+    if (alpha == out) throw Error{GP_EINVAL, "alpha and out may not alias"};
+    Plan* P = &h->P;
+    double* xs = P->vec.as<double>();
+    double* ys = xs + P->n;
+    gather_sorted(P, alpha, xs);
+    matvec_sorted(P, xs, ys, add_noise ? 1 : 0);
+    scatter_user(P, ys, out);
+    return GP_OK;
+  });
+}
+
+int gp_cg_solve(gp_plan_t h, const double* y, double* alpha, int use_x0, double tol, int max_iter,
+                int replace_every, gp_cg_info* info) {
+  return guarded([&] {
+    if (!h || !y || !alpha) throw Error{GP_EINVAL, "null argument"};
+    if (!(tol > 0) || max_iter < 0) throw Error{GP_EINVAL, "tol must be > 0, max_iter >= 0"};
+    Plan* P = &h->P;
+    auto t0 = std::chrono::steady_clock::now();
+    double* V = P->vec.as<double>();
+    double* bs = V + 6 * P->n;
+    double* xs = V + 2 * P->n;
+    gather_sorted(P, y, bs);
+    if (use_x0)
+      gather_sorted(P, alpha, xs);
+    else
+      GP_HIP(hipMemsetAsync(xs, 0, P->n * sizeof(double), P->stream));
+    int iters = 0;
+    double rr = 0;
+    int st = cg_solve_sorted(P, bs, xs, !use_x0, tol, max_iter, replace_every, &iters, &rr);
+    scatter_user(P, xs, alpha);
+    GP_HIP(hipStreamSynchronize(P->stream));
+    if (info) {
+      info->iters = iters;
+      info->status = st;
+      info->rel_res = rr;
+      info->rel_res_true = -1.0;
+      info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      info->refinements = 0;
+    }
+    if (st != GP_OK) set_error("CG reached max_iter before the tolerance");
+    return st;
+  });
+}
+
+int gp_cg_solve_refined(gp_plan_t hin, gp_plan_t hout, const double* y, double* alpha, double tol,
+                        double inner_tol, int max_iter, int max_refine, int replace_every,
+                        gp_cg_info* info) {
+  return guarded([&] {
+    if (!hin || !hout || !y || !alpha) throw Error{GP_EINVAL, "null argument"};
+    Plan* Pi = &hin->P;
+    Plan* Po = &hout->P;
+    if (Pi->n != Po->n || Pi->d != Po->d) throw Error{GP_EINVAL, "plans differ in n or d"};
+    if (Pi->stream != Po->stream) throw Error{GP_EINVAL, "plans must share a stream"};
+    auto t0 = std::chrono::steady_clock::now();
+    const int64_t n = Po->n;
+    hipStream_t s = Po->stream;
+    DevBuf rb, db, tb;
+    rb.alloc(n * sizeof(double));
+    db.alloc(n * sizeof(double));
+    tb.alloc(n * sizeof(double));
+    double* r = rb.as<double>();   // user order
+    double* dl = db.as<double>();
+    double* tmp = tb.as<double>();
+    double* Vo = Po->vec.as<double>();
+    double* Vi = Pi->vec.as<double>();
+    GP_HIP(hipMemsetAsync(alpha, 0, n * sizeof(double), s));
+    // bb
+    gather_sorted(Po, y, Vo + 6 * n);
+    const double bb = dot_sorted(Po, Vo + 6 * n, Vo + 6 * n, n);
+    int total = 0, passes = 0, st = GP_OK;
+    double rel = 1.0, inner_rel = 0;
+    while (true) {
+      // r = y - A_outer alpha  (fp64 operator)
+      gather_sorted(Po, alpha, Vo);
+      matvec_sorted(Po, Vo, Vo + n, 1);
+      scatter_user(Po, Vo + n, tmp);
+      hipLaunchKernelGGL(sub_kernel, dim3(blocks(n)), dim3(256), 0, s, n, y, tmp, r);
+      GP_CHECK_LAUNCH();
+      gather_sorted(Po, r, Vo + 7 * n);
+      const double rr = dot_sorted(Po, Vo + 7 * n, Vo + 7 * n, n);
+      rel = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+      if (rel <= tol || passes >= max_refine || total >= max_iter) break;
+      // inner solve A_inner d = r
+      const double itol = std::max(tol / std::max(rel, 1e-300), inner_tol);
+      gather_sorted(Pi, r, Vi + 6 * n);
+      GP_HIP(hipMemsetAsync(Vi + 2 * n, 0, n * sizeof(double), s));
+      int it = 0;
+      int sti = cg_solve_sorted(Pi, Vi + 6 * n, Vi + 2 * n, true, itol, max_iter - total, replace_every,
+                                &it, &inner_rel);
+      (void)sti;
+      total += it;
+      scatter_user(Pi, Vi + 2 * n, dl);
+      hipLaunchKernelGGL(axpy_kernel, dim3(blocks(n)), dim3(256), 0, s, n, 1.0, dl, alpha);
+      GP_CHECK_LAUNCH();
+      ++passes;
+    }
+    GP_HIP(hipStreamSynchronize(s));
+    st = rel <= tol ? GP_OK : GP_ENOCONV;
+    if (info) {
+      info->iters = total;
+      info->status = st;
+      info->rel_res = rel;
+      info->rel_res_true = rel;
+      info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      info->refinements = passes;
+    }
+    if (st != GP_OK) set_error("refined CG did not reach the tolerance");
+    return st;
+  });
+}
+
+int gp_posterior_mean(gp_plan_t h, const double* alpha, int64_t m, const double* targets,
+                      const double* sigma_t, const double* l_t, double* mu) {
+  return guarded([&] {
+    if (!h || !alpha || !targets || !sigma_t || !l_t || !mu) throw Error{GP_EINVAL, "null argument"};
+    if (m < 1) throw Error{GP_EINVAL, "m must be >= 1"};
+    Plan* P = &h->P;
+    // validate targets against the box and the length-scale range (host copy)
+    std::vector<double> hx(m * P->d), hl(m), hs(m);
+    GP_HIP(hipMemcpyAsync(hx.data(), targets, m * P->d * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+    GP_HIP(hipMemcpyAsync(hl.data(), l_t, m * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+    GP_HIP(hipMemcpyAsync(hs.data(), sigma_t, m * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+    GP_HIP(hipStreamSynchronize(P->stream));
+    for (int64_t i = 0; i < m; ++i) {
+      for (int r = 0; r < P->d; ++r) {
+        double xp = (hx[i * P->d + r] - P->center[r]) * P->scale;
+        if (!std::isfinite(xp)) throw Error{GP_EDOMAIN, "non-finite target"};
+        if (xp < -1.0 - 1e-12 || xp > 1.0 + 1e-12) throw Error{GP_ERANGE, "target outside the plan's box"};
+      }
+      if (!(hs[i] > 0) || !(hl[i] > 0)) throw Error{GP_EDOMAIN, "target scales must be > 0"};
+      double sp = hl[i] * P->scale * 0.70710678118654752440;
+      if (P->n_sigma > 0 && (sp < P->s_min * (1 - 1e-12) || sp > P->s_max * (1 + 1e-12)))
+        throw Error{GP_ERANGE, "target length scale outside the plan's range"};
+      if (P->n_sigma == 0 && std::fabs(sp - P->s_min) > 1e-12 * P->s_min)
+        throw Error{GP_ERANGE, "stationary plan: target length scale differs"};
+    }
+    double* xs = P->vec.as<double>();
+    gather_sorted(P, alpha, xs);
+    posterior_sorted(P, xs, m, targets, sigma_t, l_t, mu);
+    return GP_OK;
+  });
+}
+
+int gp_residual(gp_plan_t h, const double* y, const double* alpha, double* rel_res) {
+  return guarded([&] {
+    if (!h || !y || !alpha || !rel_res) throw Error{GP_EINVAL, "null argument"};
+    Plan* P = &h->P;
+    double* V = P->vec.as<double>();
+    gather_sorted(P, y, V + 6 * P->n);
+    gather_sorted(P, alpha, V + 2 * P->n);
+    double rr = 0, bb = 0;
+    residual_norms(P, V + 6 * P->n, V + 2 * P->n, &rr, &bb);
+    *rel_res = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+    return GP_OK;
+  });
+}
+
+int gp_plan_set_timing(gp_plan_t h, int enable) {
+  return guarded([&] {
+    if (!h) throw Error{GP_EINVAL, "null plan"};
+    Plan* P = &h->P;
+    GP_HIP(hipStreamSynchronize(P->stream));
+    for (auto& ev : P->events) {
+      P->pool.push_back(ev.a);
+      P->pool.push_back(ev.b);
+    }
+    P->events.clear();
+    P->timing = enable != 0;
+    return GP_OK;
+  });
+}
+
+int gp_plan_get_timing(gp_plan_t h, gp_timing* out) {
+  return guarded([&] {
+    if (!h || !out) throw Error{GP_EINVAL, "null argument"};
+    Plan* P = &h->P;
+    GP_HIP(hipStreamSynchronize(P->stream));
+    std::memset(out, 0, sizeof(*out));
+    out->n_phases = PH_COUNT;
+    for (int k = 0; k < PH_COUNT; ++k) out->name[k] = kPhaseNames[k];
+    for (auto& ev : P->events) {
+      float ms = 0;
+      GP_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
+      out->ms[ev.phase] += ms;
+      out->launches[ev.phase] += 1;
+    }
+    return GP_OK;
+  });
+}
+
+int gp_plan_set_stream(gp_plan_t h, void* stream) {
+  return guarded([&] {
+    if (!h) throw Error{GP_EINVAL, "null plan"};
+    h->P.stream = static_cast<hipStream_t>(stream);
+    return GP_OK;
+  });
+}
+
+int gp_plan_destroy(gp_plan_t h) {
+  return guarded([&] {
+    if (!h) return GP_OK;
+    (void)hipStreamSynchronize(h->P.stream);
+    delete h;
+    return GP_OK;
+  });
+}
+
+const char* gp_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,219 @@
+// Conjugate gradients on (K~ + eta^2 I) x = b  (eq:gprsolve; section 6.2 wraps the
+// matvec in CG with a relative-residual stopping rule).  Vectors are fp64 and
+// live in the plan's bin-sorted point order; dot products are two-stage
+// reductions with a fixed block count, so they are deterministic.  The step
+// lengths alpha, beta stay on the device; the host reads ||r||^2 once per
+// iteration for the stopping test.
+#include <cmath>
+
+#include "gp_internal.h"
+
+namespace gp {
+namespace {
+
+constexpr int kRedThreads = 256;
+constexpr int kRedBlocks = 512;
+
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double red[kRedThreads / 64];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < kRedThreads / 64; ++k) s += red[k];
+  return s;  // valid in thread 0
+}
+
+__global__ __launch_bounds__(kRedThreads) void dot_partial(int64_t n, const double* __restrict__ a,
+                                                           const double* __restrict__ b,
+                                                           double* __restrict__ part) {
+  double v = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kRedThreads)
+    v += a[i] * b[i];
+  v = block_sum(v);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+// S layout: 0 rr, 1 pAp, 2 rr_new, 3 bb, 4 beta, 5 scratch
+// mode 0: S[slot] = sum; mode 1 (rr update): S[2] = sum, S[4] = sum / S[0], S[0] = sum
+__global__ __launch_bounds__(kRedThreads) void dot_final(int nparts, const double* __restrict__ part,
+                                                         double* __restrict__ S, int slot, int mode) {
+  double v = 0;
+  for (int i = threadIdx.x; i < nparts; i += kRedThreads) v += part[i];
+  v = block_sum(v);
+  if (threadIdx.x == 0) {
+    if (mode == 0) {
+      S[slot] = v;
+    } else {
+      S[2] = v;
+      S[4] = v / S[0];
+      S[0] = v;
+    }
+  }
+}
+
+// x += a p ; r -= a Ap ; partial sums of r.r   with a = S[0]/S[1]
+__global__ __launch_bounds__(kRedThreads) void update_xr(int64_t n, const double* __restrict__ S,
+                                                         double* __restrict__ x,
+                                                         double* __restrict__ r,
+                                                         const double* __restrict__ p,
+                                                         const double* __restrict__ Ap,
+                                                         double* __restrict__ part) {
+  const double a = S[0] / S[1];
+  double v = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kRedThreads) {
+    x[i] += a * p[i];
+    const double ri = r[i] - a * Ap[i];
+    r[i] = ri;
+    v += ri * ri;
+  }
+  v = block_sum(v);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+// p = r + beta p, beta = S[4]
+__global__ void update_p(int64_t n, const double* __restrict__ S, const double* __restrict__ r,
+                         double* __restrict__ p) {
+  const double b = S[4];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = r[i] + b * p[i];
+}
+
+// r = b - Ax
+__global__ void residual(int64_t n, const double* __restrict__ b, const double* __restrict__ Ax,
+                         double* __restrict__ r) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    r[i] = b[i] - Ax[i];
+}
+
+__global__ void copy_vec(int64_t n, const double* __restrict__ a, double* __restrict__ b) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = a[i];
+}
+
+unsigned nblk(int64_t n) {
+  int64_t b = (n + kRedThreads - 1) / kRedThreads;
+  return (unsigned)std::min<int64_t>(std::max<int64_t>(b, 1), kRedBlocks);
+}
+
+struct Scratch {
+  DevBuf part, S;
+  double* hS = nullptr;
+  Scratch() {
+    part.alloc(kRedBlocks * sizeof(double));
+    S.alloc(8 * sizeof(double));
+    GP_HIP(hipHostMalloc((void**)&hS, 8 * sizeof(double), hipHostMallocDefault));
+  }
+  ~Scratch() {
+    if (hS) (void)hipHostFree(hS);
+  }
+};
+
+void dot_into(Plan* P, Scratch& sc, const double* a, const double* b, int slot) {
+  const unsigned nb = nblk(P->n);
+  hipLaunchKernelGGL(dot_partial, dim3(nb), dim3(kRedThreads), 0, P->stream, P->n, a, b,
+                     sc.part.as<double>());
+  hipLaunchKernelGGL(dot_final, dim3(1), dim3(kRedThreads), 0, P->stream, (int)nb,
+                     sc.part.as<double>(), sc.S.as<double>(), slot, 0);
+  GP_CHECK_LAUNCH();
+}
+
+double read_slot(Plan* P, Scratch& sc, int slot) {
+  GP_HIP(hipMemcpyAsync(sc.hS + slot, sc.S.as<double>() + slot, sizeof(double),
+                        hipMemcpyDeviceToHost, P->stream));
+  GP_HIP(hipStreamSynchronize(P->stream));
+  return sc.hS[slot];
+}
+
+}  // namespace
+
+double dot_sorted(Plan* P, const double* a, const double* b, int64_t) {
+  Scratch sc;
+  dot_into(P, sc, a, b, 5);
+  return read_slot(P, sc, 5);
+}
+
+void residual_norms(Plan* P, const double* b, const double* x, double* rr, double* bb) {
+  double* t = P->vec.as<double>() + 7 * P->n;
+  matvec_sorted(P, x, t, 1);
+  hipLaunchKernelGGL(residual, dim3(nblk(P->n)), dim3(kRedThreads), 0, P->stream, P->n, b, t, t);
+  GP_CHECK_LAUNCH();
+  Scratch sc;
+  dot_into(P, sc, t, t, 5);
+  *rr = read_slot(P, sc, 5);
+  dot_into(P, sc, b, b, 5);
+  *bb = read_slot(P, sc, 5);
+}
+
+// x: in = initial guess (or zero if x_zero), out = solution (sorted order).
+// Returns GP_OK or GP_ENOCONV.
+int cg_solve_sorted(Plan* P, const double* b, double* x, bool x_zero, double tol, int max_iter,
+                    int replace_every, int* iters, double* rel_res) {
+  const int64_t n = P->n;
+  double* V = P->vec.as<double>();
+  double* r = V + 3 * n;
+  double* p = V + 4 * n;
+  double* Ap = V + 5 * n;
+  Scratch sc;
+  hipStream_t s = P->stream;
+  const unsigned nb = nblk(n);
+
+  if (x_zero) {
+    hipLaunchKernelGGL(copy_vec, dim3(nb), dim3(kRedThreads), 0, s, n, b, r);
+  } else {
+    matvec_sorted(P, x, Ap, 1);
+    hipLaunchKernelGGL(residual, dim3(nb), dim3(kRedThreads), 0, s, n, b, Ap, r);
+  }
+  hipLaunchKernelGGL(copy_vec, dim3(nb), dim3(kRedThreads), 0, s, n, r, p);
+  GP_CHECK_LAUNCH();
+  dot_into(P, sc, b, b, 3);
+  dot_into(P, sc, r, r, 0);
+  const double bb = read_slot(P, sc, 3);
+  double rr = read_slot(P, sc, 0);
+  if (bb == 0.0) {
+    *iters = 0;
+    *rel_res = 0;
+    return GP_OK;
+  }
+  const double stop2 = tol * tol * bb;
+  int it = 0;
+  while (rr > stop2 && it < max_iter) {
+    ++it;
+    matvec_sorted(P, p, Ap, 1);
+    {
+      PhaseScope ps(P, PH_CG);
+      dot_into(P, sc, p, Ap, 1);
+      hipLaunchKernelGGL(update_xr, dim3(nb), dim3(kRedThreads), 0, s, n, sc.S.as<double>(), x,
+                         r, p, Ap, sc.part.as<double>());
+      GP_CHECK_LAUNCH();
+    }
+    if (replace_every > 0 && it % replace_every == 0) {
+      matvec_sorted(P, x, Ap, 1);
+      hipLaunchKernelGGL(residual, dim3(nb), dim3(kRedThreads), 0, s, n, b, Ap, r);
+      hipLaunchKernelGGL(dot_partial, dim3(nb), dim3(kRedThreads), 0, s, n, r, r,
+                         sc.part.as<double>());
+      GP_CHECK_LAUNCH();
+    }
+    {
+      PhaseScope ps(P, PH_CG);
+      hipLaunchKernelGGL(dot_final, dim3(1), dim3(kRedThreads), 0, s, (int)nb,
+                         sc.part.as<double>(), sc.S.as<double>(), 0, 1);
+      hipLaunchKernelGGL(update_p, dim3(nb), dim3(kRedThreads), 0, s, n, sc.S.as<double>(), r, p);
+      GP_CHECK_LAUNCH();
+    }
+    rr = read_slot(P, sc, 2);
+    if (!std::isfinite(rr)) throw Error{GP_EDEVICE, "CG breakdown: non-finite residual"};
+  }
+  *iters = it;
+  *rel_res = std::sqrt(rr / bb);
+  return rr <= stop2 ? GP_OK : GP_ENOCONV;
+}
+
+}  // namespace gp

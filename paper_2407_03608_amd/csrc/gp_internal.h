@@ -1,0 +1,184 @@
+// Internal declarations shared by the gpnufft translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/gpnufft.h"
+
+namespace gp {
+
+// ------------------------------------------------------------------ errors --
+void set_error(const std::string& msg);
+void clear_error();
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+#define GP_HIP(call)                                                                    \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      throw ::gp::Error{GP_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+#define GP_CHECK_LAUNCH() GP_HIP(hipGetLastError())
+
+// --------------------------------------------------------- device buffers --
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void alloc(size_t b);
+  void release();
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Lengths the FFT pass kernel is compiled for (2^a and 3*2^a, 8 .. 8192).
+bool fft_length_supported(int L);
+
+// One batched pass of 1-D FFTs along one axis of a strided array:
+// element (o, pos, c) of the input lives at in[o*in_os + i*inner + c] where
+// i = (pos - in_start) mod L and i < n_in (other positions are zero); the
+// output keeps positions out_start .. out_start + n_out - 1 (mod L) at
+// out[o*out_os + i*inner + c].  sign = -1 forward, +1 inverse (unnormalised).
+// tw4 != null applies the four-step twiddle exp(sign 2 pi i pos*o / L4) on load
+// (tw4_at_load = 1) or on store (0); tw4 holds exp(-2 pi i k / L4), k < L4.
+struct FftPass {
+  int L;
+  int64_t n_outer;
+  int64_t inner;
+  int64_t in_os, out_os;
+  int n_in, in_start, n_out, out_start;
+  int sign;
+  const void* tw4 = nullptr;
+  int64_t L4 = 0;
+  int tw4_at_load = 1;
+};
+void fft_pass(int fp64, const FftPass& p, const void* in, void* out, const void* twiddles,
+              hipStream_t s);
+
+// ------------------------------------------------------------------- plan --
+struct Plan {
+  // problem
+  int d = 0;
+  int64_t n = 0;
+  int precision = GP_FP64;
+  double nu = 0, eta = 0;
+  bool se = false;
+  // mapping into [-1,1]^d
+  double center[3] = {0, 0, 0};
+  double scale = 1;
+  // approximation parameters (section 3.5)
+  double t_min = 0, t_max = 0;
+  int n_t = 0;
+  double s_min = 0, s_max = 0;
+  int n_sigma = 0;
+  double dw = 0;
+  int64_t M = 0;
+  double pred_tail = 0;
+  int m_capped = 0;
+  double l_range_lo = 0, l_range_hi = 0;  // admissible user length scales (mapped: *scale)
+  // spreading / FFT geometry
+  double nufft_tol = 0;
+  int w = 0;
+  double beta = 0;
+  int nf[3] = {1, 1, 1};
+  int lo[3] = {0, 0, 0};
+  int na[3] = {1, 1, 1};      // active-box length (multiple of tile)
+  int tile[3] = {1, 1, 1};
+  int nbins[3] = {1, 1, 1};
+  int64_t n_bins = 1;
+  int fourstep = 0;           // d = 1 and nf > 8192: nf = L1 * L2
+  int L1 = 0, L2 = 0;
+  int nk = 0;                 // real grids = N_sigma + 1
+  int npair = 0;              // complex grids = ceil(nk/2)
+  int nt_eff = 0;             // t nodes (N_t + 1, or 1 for SE)
+  int64_t mcount = 0;         // (2M+1)
+  // host copies of the tables (for info / tests)
+  std::vector<double> sig_nodes, bary, vt, chi;
+  // device data
+  hipStream_t stream = nullptr;
+  DevBuf perm;                // int32  sorted -> caller index
+  DevBuf cell;                // int32  [d][n] start cell in the active box
+  DevBuf frac;                // T      [d][n] offset of the first cell from the point
+  DevBuf spn;                 // double [n] sigma_p of the point (mapped)
+  DevBuf pref;                // double [n] s(x) (2/(pi l'^2))^(d/4)
+  DevBuf bin_start;           // int32  [n_bins + 1]
+  DevBuf nodes_d;             // double [nk] sigma_k
+  DevBuf bary_d;              // double [nk] barycentric weights
+  DevBuf gtab;                // T [nt][nk][M+1]: C_kj * exp(-tau_kj n^2) for dim 0
+  DevBuf etab;                // T [nt][nk][M+1]: exp(-tau_kj n^2) for dims >= 1
+  DevBuf vtd;                 // T [nt] v~_j
+  DevBuf dec;                 // T [d][M+1] 1/psi^(2 pi n / nf_r)
+  DevBuf tw[3];               // FFT twiddles per distinct length (T complex)
+  DevBuf tw4;                 // four-step twiddles (1-D, T complex, length nf)
+  DevBuf gridA, gridB, gridB2, gridC;
+  DevBuf vec;                 // fp64 scratch vectors for matvec / CG (sorted order)
+  size_t device_bytes = 0;
+  // optional per-phase event timing
+  bool timing = false;
+  struct Ev {
+    int phase;
+    hipEvent_t a, b;
+  };
+  std::vector<Ev> events;
+  std::vector<hipEvent_t> pool;
+  ~Plan();
+};
+
+enum Phase {
+  PH_SPREAD = 0,
+  PH_FFT_FWD0 = 1,
+  PH_MODE = 4,
+  PH_FFT_INV2 = 5,
+  PH_INTERP = 8,
+  PH_CG = 9,
+  PH_COUNT = 10
+};
+extern const char* const kPhaseNames[PH_COUNT];
+
+// Brackets a group of launches with HIP events when the plan times itself.
+struct PhaseScope {
+  Plan* P;
+  int phase;
+  hipEvent_t b = nullptr;
+  PhaseScope(Plan* p, int ph);
+  ~PhaseScope();
+};
+
+// plan.hip
+int build_plan(int d, int64_t n, const double* pts, const double* sigma, const double* l,
+               double nu, double eta, double tol, const gp_opts* opts, Plan* P, bool query_only,
+               size_t* bytes_out);
+
+// nufft.hip: y = K~ x (+ eta^2 x) with x, y fp64 in SORTED order on the plan stream.
+void matvec_sorted(Plan* P, const double* x_sorted, double* y_sorted, int add_noise);
+// Evaluate the type-2 + combine step at arbitrary mapped targets after a forward
+// pass of x_sorted; used by the posterior mean.
+void posterior_sorted(Plan* P, const double* x_sorted, int64_t m, const double* tpts,
+                      const double* tsig, const double* tl, double* mu);
+// gather / scatter between caller and sorted order
+void gather_sorted(Plan* P, const double* x_user, double* x_sorted);
+void scatter_user(Plan* P, const double* x_sorted, double* x_user);
+
+// cg.hip
+int cg_solve_sorted(Plan* P, const double* b, double* x, bool x_zero, double tol, int max_iter,
+                    int replace_every, int* iters, double* rel_res);
+double dot_sorted(Plan* P, const double* a, const double* b, int64_t n);
+// ||b - (K~ + eta^2 I) x||^2 and ||b||^2 (sorted order)
+void residual_norms(Plan* P, const double* b, const double* x, double* rr, double* bb);
+
+}  // namespace gp
+
+struct gp_plan_s {
+  gp::Plan P;
+};

@@ -1,0 +1,760 @@
+// The matvec y = K~ x of section 4.2 on gfx950.
+//
+//  step 1+2a  spread_kernel   c_{k,i} = w_k(x_i) x_i (eq:c) spread onto the fine
+//                             grids with the exponential-of-semicircle window
+//  step 2b    fft passes      forward FFT of every grid (pruned)
+//  step 3     mode_kernel     a_k'[n] = sum_j v~_j G^_k'j[n] sum_k G^_kj[n] b_k[n]
+//                             with the window deconvolution folded in
+//  step 4a    fft passes      inverse FFT (pruned)
+//  step 4b+5  interp_kernel   beta_{k,i} by interpolation, y_i = sum_k w_k(x_i) beta_{k,i}
+//                             (+ eta^2 x_i)
+//
+// Real grids travel in complex pairs: grid 2g is the real part and grid 2g+1
+// the imaginary part of complex grid g, so every FFT is complex-to-complex and
+// the mode kernel separates the two spectra with b(n) = (Z(n) + conj Z(-n))/2.
+//
+// Spreading is a gather: each workgroup owns one tile of the active fine grid,
+// collects every point whose window reaches it (the points are bin-sorted by
+// the tile of their first window cell, so the sources are the 2^d (or more)
+// neighbouring bins), accumulates in LDS with LDS atomics and writes its tile
+// with plain coalesced stores.  No global atomics and no zero-fill pass.
+#include <cmath>
+
+#include "gp_internal.h"
+
+namespace gp {
+
+void build_records_into(Plan* P, int64_t n, const double* pts, const double* sig,
+                        const double* l, DevBuf& perm, DevBuf& cell, DevBuf& frac, DevBuf& spn,
+                        DevBuf& pref, DevBuf& bin_start, int* out_of_box);
+
+namespace {
+
+template <typename T> struct V2;
+template <> struct V2<double> { using type = double2; };
+template <> struct V2<float> { using type = float2; };
+
+constexpr int kThreads = 256;
+constexpr int kPB = 64;      // points staged per batch
+constexpr int kGC = 8;       // max complex grids per chunk
+
+struct NuArgs {
+  int64_t n;
+  int nk, npair, w;
+  double beta;
+  int tile[3], nbins[3], na[3];
+  int64_t gstride[3];  // element strides of the active grid (dim 0 contiguous)
+  int64_t pair_stride;
+  int64_t grid_off;
+  int g0, gc, nsrc;
+  double eta2;
+  int add_noise, first_chunk;
+};
+
+template <typename T> __device__ __forceinline__ T es_kernel(T z, T two_over_w, T beta) {
+  T a = z * two_over_w;
+  T q = T(1) - a * a;
+  return q >= T(0) ? exp(beta * (sqrt(q) - T(1))) : T(0);
+}
+
+// Lagrange basis on the Chebyshev-Lobatto nodes (eq:chebscheme) in barycentric
+// form: P_k(s) = (lam_k/(s - s_k)) / sum_j lam_j/(s - s_j); P_k = delta at a node.
+__device__ __forceinline__ double bary_den(double s, const double* __restrict__ nodes,
+                                           const double* __restrict__ bary, int nk, int* hit) {
+  double den = 0;
+  *hit = -1;
+  for (int k = 0; k < nk; ++k) {
+    double dk = s - nodes[k];
+    if (dk == 0.0) {
+      *hit = k;
+      return 1.0;
+    }
+    den += bary[k] / dk;
+  }
+  return den;
+}
+__device__ __forceinline__ double bary_p(int k, double s, double den, int hit,
+                                         const double* __restrict__ nodes,
+                                         const double* __restrict__ bary) {
+  if (hit >= 0) return k == hit ? 1.0 : 0.0;
+  return bary[k] / (s - nodes[k]) / den;
+}
+
+// ---------------------------------------------------------------- spread ----
+template <typename T, int D, int WT>
+__global__ __launch_bounds__(kThreads) void spread_kernel(
+    NuArgs a, const double* __restrict__ x, const int* __restrict__ cell,
+    const T* __restrict__ frac, const double* __restrict__ spn, const double* __restrict__ pref,
+    const int* __restrict__ bin_start, const double* __restrict__ nodes,
+    const double* __restrict__ bary, typename V2<T>::type* __restrict__ grid) {
+  using V = typename V2<T>::type;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tc0 = a.tile[0], tc1 = D > 1 ? a.tile[1] : 1, tc2 = D > 2 ? a.tile[2] : 1;
+  const int tcells = tc0 * tc1 * tc2;
+  V* acc = reinterpret_cast<V*>(smem);
+  T* s_psi = reinterpret_cast<T*>(acc + (size_t)a.gc * tcells);  // [kPB][D][WT]
+  T* s_c = s_psi + kPB * D * WT;                                  // [kPB][2*kGC]
+  int* s_cell = reinterpret_cast<int*>(s_c + kPB * 2 * kGC);      // [kPB][D]
+
+  int tcoord[3] = {0, 0, 0}, t0[3] = {0, 0, 0};
+  {
+    int64_t tb = blockIdx.x;
+    for (int r = 0; r < D; ++r) {
+      tcoord[r] = (int)(tb % a.nbins[r]);
+      tb /= a.nbins[r];
+      t0[r] = tcoord[r] * a.tile[r];
+    }
+  }
+  for (int e = threadIdx.x; e < a.gc * tcells; e += kThreads) acc[e] = V{T(0), T(0)};
+  __syncthreads();
+
+  const T two_over_w = T(2) / T(a.w);
+  const T beta = (T)a.beta;
+  int nsrc_tot = 1;
+  for (int r = 0; r < D; ++r) nsrc_tot *= a.nsrc;
+  int rows = 1;
+  for (int r = 1; r < D; ++r) rows *= a.w;
+
+  for (int sb = 0; sb < nsrc_tot; ++sb) {
+    int64_t bin = 0, mul = 1;
+    bool ok = true;
+    int q = sb;
+    for (int r = 0; r < D; ++r) {
+      int br = tcoord[r] - (q % a.nsrc);
+      q /= a.nsrc;
+      if (br < 0) ok = false;
+      bin += (int64_t)br * mul;
+      mul *= a.nbins[r];
+    }
+    if (!ok) continue;
+    const int p0 = bin_start[bin], p1 = bin_start[bin + 1];
+    for (int pb = p0; pb < p1; pb += kPB) {
+      const int np = min(kPB, p1 - pb);
+      if (threadIdx.x < np) {
+        const int64_t i = pb + threadIdx.x;
+        for (int r = 0; r < D; ++r) {
+          s_cell[threadIdx.x * D + r] = cell[r * a.n + i];
+          T del = frac[r * a.n + i];
+#pragma unroll
+          for (int qq = 0; qq < WT; ++qq)
+            s_psi[(threadIdx.x * D + r) * WT + qq] =
+                qq < a.w ? es_kernel<T>(del + T(qq), two_over_w, beta) : T(0);
+        }
+        const double sp = spn[i];
+        int hit;
+        const double den = bary_den(sp, nodes, bary, a.nk, &hit);
+        const double sc = pref[i] * x[i];
+        for (int kk = 0; kk < 2 * kGC; ++kk) {
+          const int k = 2 * a.g0 + kk;
+          double v = 0;
+          if (kk < 2 * a.gc && k < a.nk) v = sc * bary_p(k, sp, den, hit, nodes, bary);
+          s_c[threadIdx.x * 2 * kGC + kk] = (T)v;
+        }
+      }
+      __syncthreads();
+      const int nitems = np * rows * a.gc;
+      for (int it = threadIdx.x; it < nitems; it += kThreads) {
+        const int p = it % np;
+        const int rest = it / np;
+        const int row = rest % rows;
+        const int g = rest / rows;
+        // outer (dims >= 1) cell offsets of this row
+        int loc[3] = {0, 0, 0};
+        T wv = T(1);
+        bool inside = true;
+        int rr = row;
+        for (int r = 1; r < D; ++r) {
+          const int qr = rr % a.w;
+          rr /= a.w;
+          const int cr = s_cell[p * D + r] + qr - t0[r];
+          if (cr < 0 || cr >= a.tile[r]) inside = false;
+          loc[r] = cr;
+          wv *= s_psi[(p * D + r) * WT + qr];
+        }
+        if (!inside) continue;
+        const T c0 = s_c[p * 2 * kGC + 2 * g], c1 = s_c[p * 2 * kGC + 2 * g + 1];
+        const int base0 = s_cell[p * D] - t0[0];
+        V* accg = acc + (size_t)g * tcells + (loc[2] * tc1 + loc[1]) * tc0;
+#pragma unroll
+        for (int q0 = 0; q0 < WT; ++q0) {
+          const int c = base0 + q0;
+          if (q0 < a.w && c >= 0 && c < tc0) {
+            const T v = wv * s_psi[(p * D) * WT + q0];
+            atomicAdd(&accg[c].x, c0 * v);
+            atomicAdd(&accg[c].y, c1 * v);
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // write the tile (exclusively owned: plain stores)
+  for (int e = threadIdx.x; e < a.gc * tcells; e += kThreads) {
+    const int g = e / tcells;
+    int c = e - g * tcells;
+    const int l0 = c % tc0;
+    c /= tc0;
+    const int l1 = c % tc1;
+    const int l2 = c / tc1;
+    const int64_t gi = a.grid_off + (int64_t)(t0[0] + l0) * a.gstride[0] +
+                       (int64_t)(t0[1] + l1) * a.gstride[1] + (int64_t)(t0[2] + l2) * a.gstride[2];
+    grid[(int64_t)(a.g0 + g) * a.pair_stride + gi] = acc[e];
+  }
+}
+
+// ---------------------------------------------------------------- interp ----
+// One workgroup per bin.  For each chunk of complex grids, the bin's tile plus
+// its (w-1) halo is staged in LDS; every (point, grid pair) item sums its
+// window and adds w_2g beta_2g + w_2g+1 beta_2g+1 into the point's accumulator.
+template <typename T, int D, int WT>
+__global__ __launch_bounds__(kThreads) void interp_kernel(
+    NuArgs a, const typename V2<T>::type* __restrict__ grid, const int* __restrict__ cell,
+    const T* __restrict__ frac, const double* __restrict__ spn, const double* __restrict__ pref,
+    const int* __restrict__ bin_start, const double* __restrict__ nodes,
+    const double* __restrict__ bary, const double* __restrict__ x, double* __restrict__ y) {
+  using V = typename V2<T>::type;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int pc0 = a.tile[0] + a.w - 1;
+  const int pc1 = D > 1 ? a.tile[1] + a.w - 1 : 1;
+  const int pc2 = D > 2 ? a.tile[2] + a.w - 1 : 1;
+  const int pcells = pc0 * pc1 * pc2;
+  V* tileA = reinterpret_cast<V*>(smem);                               // [gc][pcells]
+  T* s_psi = reinterpret_cast<T*>(tileA + (size_t)a.gc * pcells);      // [kPB][D][WT]
+  T* s_wk = s_psi + kPB * D * WT;                                      // [kPB][2*kGC]
+  double* s_acc = reinterpret_cast<double*>(s_wk + kPB * 2 * kGC);    // [kPB]
+  int* s_cell = reinterpret_cast<int*>(s_acc + kPB);                   // [kPB][D]
+
+  const int64_t bin = blockIdx.x;
+  const int p0 = bin_start[bin], p1 = bin_start[bin + 1];
+  if (p0 == p1) return;
+  int t0[3] = {0, 0, 0};
+  {
+    int64_t tb = bin;
+    for (int r = 0; r < D; ++r) {
+      t0[r] = (int)(tb % a.nbins[r]) * a.tile[r];
+      tb /= a.nbins[r];
+    }
+  }
+  // stage the padded tile of the chunk's grids
+  for (int e = threadIdx.x; e < a.gc * pcells; e += kThreads) {
+    const int g = e / pcells;
+    int c = e - g * pcells;
+    const int l0 = c % pc0;
+    c /= pc0;
+    const int l1 = c % pc1;
+    const int l2 = c / pc1;
+    V v = V{T(0), T(0)};
+    const int c0 = t0[0] + l0, c1 = t0[1] + l1, c2 = t0[2] + l2;
+    if (c0 < a.na[0] && (D < 2 || c1 < a.na[1]) && (D < 3 || c2 < a.na[2]))
+      v = grid[(int64_t)(a.g0 + g) * a.pair_stride + a.grid_off + (int64_t)c0 * a.gstride[0] +
+               (int64_t)c1 * a.gstride[1] + (int64_t)c2 * a.gstride[2]];
+    tileA[e] = v;
+  }
+  __syncthreads();
+
+  const T two_over_w = T(2) / T(a.w);
+  const T beta = (T)a.beta;
+  int cellsw = 1;
+  for (int r = 1; r < D; ++r) cellsw *= a.w;
+  for (int pb = p0; pb < p1; pb += kPB) {
+    const int np = min(kPB, p1 - pb);
+    if (threadIdx.x < np) {
+      const int64_t i = pb + threadIdx.x;
+      for (int r = 0; r < D; ++r) {
+        s_cell[threadIdx.x * D + r] = cell[r * a.n + i] - t0[r];
+        T del = frac[r * a.n + i];
+#pragma unroll
+        for (int qq = 0; qq < WT; ++qq)
+          s_psi[(threadIdx.x * D + r) * WT + qq] =
+              qq < a.w ? es_kernel<T>(del + T(qq), two_over_w, beta) : T(0);
+      }
+      const double sp = spn[i];
+      int hit;
+      const double den = bary_den(sp, nodes, bary, a.nk, &hit);
+      for (int kk = 0; kk < 2 * kGC; ++kk) {
+        const int k = 2 * a.g0 + kk;
+        double v = 0;
+        if (kk < 2 * a.gc && k < a.nk) v = pref[i] * bary_p(k, sp, den, hit, nodes, bary);
+        s_wk[threadIdx.x * 2 * kGC + kk] = (T)v;
+      }
+      s_acc[threadIdx.x] = 0.0;
+    }
+    __syncthreads();
+    const int nitems = np * a.gc;
+    for (int it = threadIdx.x; it < nitems; it += kThreads) {
+      const int p = it % np;
+      const int g = it / np;
+      const V* tg = tileA + (size_t)g * pcells;
+      T sx = 0, sy = 0;
+      for (int row = 0; row < cellsw; ++row) {
+        int rr = row;
+        T wv = T(1);
+        int off = 0, mulo = pc0;
+        for (int r = 1; r < D; ++r) {
+          const int qr = rr % a.w;
+          rr /= a.w;
+          wv *= s_psi[(p * D + r) * WT + qr];
+          off += (s_cell[p * D + r] + qr) * mulo;
+          mulo *= (r == 1 ? pc1 : pc2);
+        }
+        const V* tr = tg + off + s_cell[p * D];
+        T rx = 0, ry = 0;
+#pragma unroll
+        for (int q0 = 0; q0 < WT; ++q0) {
+          if (q0 < a.w) {
+            const T ps = s_psi[(p * D) * WT + q0];
+            const V gv = tr[q0];
+            rx += ps * gv.x;
+            ry += ps * gv.y;
+          }
+        }
+        sx += wv * rx;
+        sy += wv * ry;
+      }
+      const double contrib = (double)s_wk[p * 2 * kGC + 2 * g] * (double)sx +
+                             (double)s_wk[p * 2 * kGC + 2 * g + 1] * (double)sy;
+      atomicAdd(&s_acc[p], contrib);
+    }
+    __syncthreads();
+    if (threadIdx.x < np) {
+      const int64_t i = pb + threadIdx.x;
+      double base = a.first_chunk ? (a.add_noise ? a.eta2 * x[i] : 0.0) : y[i];
+      y[i] = base + s_acc[threadIdx.x];
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ mode ----
+struct ModeArgs {
+  int d;
+  int64_t M, mc, F;       // mc = 2M+1, F = mc^d
+  int nk, npair, nt;
+  int64_t pair_stride;
+  int fourstep;
+  int64_t nf, L1, L2;
+};
+
+__device__ __forceinline__ int64_t mode_store(const ModeArgs& a, int64_t f, const int64_t* nv) {
+  if (!a.fourstep) return f;
+  int64_t k = nv[0] % a.nf;
+  if (k < 0) k += a.nf;
+  return (k % a.L2) * a.L1 + (k / a.L2);
+}
+
+// Each thread owns a mode pair (n, -n) of every complex grid: it unpacks the two
+// real spectra b_2g, b_2g+1, deconvolves, applies
+//   a_k'[n] = sum_j v~_j G^_k'j[n] sum_k G^_kj[n] b_k[n]     (step 3, rem:step3 direct)
+// re-deconvolves and packs the result back in place.
+template <typename T, int NK>
+__global__ __launch_bounds__(kThreads) void mode_kernel(
+    ModeArgs a, typename V2<T>::type* __restrict__ C, const T* __restrict__ gtab,
+    const T* __restrict__ etab, const T* __restrict__ vt, const T* __restrict__ dec) {
+  using V = typename V2<T>::type;
+  const int64_t f = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t half = (a.F + 1) / 2;
+  if (f >= half) return;
+  const int64_t fc = a.F - 1 - f;
+  int64_t nv[3] = {0, 0, 0}, nvc[3] = {0, 0, 0};
+  int64_t an[3] = {0, 0, 0};
+  {
+    int64_t q = f;
+    for (int r = 0; r < a.d; ++r) {
+      nv[r] = q % a.mc - a.M;
+      q /= a.mc;
+      nvc[r] = -nv[r];
+      an[r] = nv[r] < 0 ? -nv[r] : nv[r];
+    }
+  }
+  const int64_t M1 = a.M + 1;
+  T D = T(1);
+  for (int r = 0; r < a.d; ++r) D *= dec[r * M1 + an[r]];
+  const int64_t s0 = mode_store(a, f, nv), s1 = mode_store(a, fc, nvc);
+  V b[NK], acc[NK];
+#pragma unroll
+  for (int g = 0; g < NK / 2; ++g) {
+    V z = V{T(0), T(0)}, zc = V{T(0), T(0)};
+    if (g < a.npair) {
+      z = C[g * a.pair_stride + s0];
+      zc = C[g * a.pair_stride + s1];
+    }
+    b[2 * g] = V{T(0.5) * (z.x + zc.x) * D, T(0.5) * (z.y - zc.y) * D};
+    b[2 * g + 1] = V{T(0.5) * (z.y + zc.y) * D, T(-0.5) * (z.x - zc.x) * D};
+    acc[2 * g] = V{T(0), T(0)};
+    acc[2 * g + 1] = V{T(0), T(0)};
+  }
+  const int nk = a.nk;
+  for (int j = 0; j < a.nt; ++j) {
+    const T* g0 = gtab + ((int64_t)j * nk) * M1 + an[0];
+    const T* e1 = etab + ((int64_t)j * nk) * M1 + an[1];
+    const T* e2 = etab + ((int64_t)j * nk) * M1 + an[2];
+    T gk[NK];
+    V s = V{T(0), T(0)};
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      T g = T(0);
+      if (k < nk) {
+        g = g0[k * M1];
+        if (a.d > 1) g *= e1[k * M1];
+        if (a.d > 2) g *= e2[k * M1];
+      }
+      gk[k] = g;
+      s.x += g * b[k].x;
+      s.y += g * b[k].y;
+    }
+    const T v = vt[j];
+    s.x *= v;
+    s.y *= v;
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      acc[k].x += gk[k] * s.x;
+      acc[k].y += gk[k] * s.y;
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < NK / 2; ++g) {
+    if (g >= a.npair) break;
+    const V p = V{acc[2 * g].x * D, acc[2 * g].y * D};
+    const V q = V{acc[2 * g + 1].x * D, acc[2 * g + 1].y * D};
+    C[g * a.pair_stride + s0] = V{p.x - q.y, p.y + q.x};
+    if (s1 != s0) C[g * a.pair_stride + s1] = V{p.x + q.y, -p.y + q.x};
+  }
+}
+
+// 1-D four-step: zero the spectrum outside {-M..M} before the inverse transform.
+template <typename T>
+__global__ void zero_band_kernel(typename V2<T>::type* C, int64_t nf, int64_t L1, int64_t L2,
+                                 int64_t M, int npair) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nf * npair) return;
+  const int64_t idx = e % nf;
+  const int64_t k2 = idx / L1, k1 = idx % L1;
+  const int64_t k = k2 + L2 * k1;
+  const int64_t n = k <= nf / 2 ? k : k - nf;
+  if (n > M || n < -M) C[e] = typename V2<T>::type{T(0), T(0)};
+}
+
+__global__ void gather_kernel(int64_t n, const int* __restrict__ perm, const double* __restrict__ u,
+                              double* __restrict__ s) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) s[i] = u[perm[i]];
+}
+__global__ void scatter_kernel(int64_t n, const int* __restrict__ perm, const double* __restrict__ s,
+                               double* __restrict__ u) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) u[perm[i]] = s[i];
+}
+
+// ------------------------------------------------------------- launchers ----
+int wt_for(int w) { return w <= 8 ? 8 : 16; }
+
+template <typename T>
+size_t spread_smem(const Plan* P, int gc, int WT) {
+  size_t tcells = (size_t)P->tile[0] * P->tile[1] * P->tile[2];
+  return gc * tcells * sizeof(typename V2<T>::type) + kPB * P->d * WT * sizeof(T) +
+         kPB * 2 * kGC * sizeof(T) + kPB * P->d * sizeof(int) + 16;
+}
+template <typename T>
+size_t interp_smem(const Plan* P, int gc, int WT) {
+  size_t pc = 1;
+  for (int r = 0; r < P->d; ++r) pc *= (size_t)(P->tile[r] + P->w - 1);
+  return gc * pc * sizeof(typename V2<T>::type) + kPB * P->d * WT * sizeof(T) +
+         kPB * 2 * kGC * sizeof(T) + kPB * sizeof(double) + kPB * P->d * sizeof(int) + 16;
+}
+
+constexpr size_t kSmemCap = 64 * 1024;
+
+NuArgs nu_args(const Plan* P) {
+  NuArgs a;
+  a.n = P->n;
+  a.nk = P->nk;
+  a.npair = P->npair;
+  a.w = P->w;
+  a.beta = P->beta;
+  for (int r = 0; r < 3; ++r) {
+    a.tile[r] = P->tile[r];
+    a.nbins[r] = P->nbins[r];
+    a.na[r] = P->na[r];
+  }
+  a.gstride[0] = 1;
+  a.gstride[1] = P->d > 1 ? P->na[0] : 0;
+  a.gstride[2] = P->d > 2 ? (int64_t)P->na[0] * P->na[1] : 0;
+  if (P->d == 1) {
+    a.pair_stride = P->fourstep ? P->nf[0] : P->na[0];
+    a.grid_off = P->fourstep ? P->lo[0] : 0;
+  } else {
+    a.pair_stride = (int64_t)P->na[0] * P->na[1] * P->na[2];
+    a.grid_off = 0;
+  }
+  a.nsrc = (P->w - 2) / P->tile[0] + 2;
+  for (int r = 1; r < P->d; ++r) a.nsrc = std::max(a.nsrc, (P->w - 2) / P->tile[r] + 2);
+  a.g0 = 0;
+  a.gc = 0;
+  a.eta2 = P->eta * P->eta;
+  a.add_noise = 0;
+  a.first_chunk = 1;
+  return a;
+}
+
+template <typename T, int D, int WT>
+void launch_spread(Plan* P, const double* xs) {
+  PhaseScope ps(P, PH_SPREAD);
+  NuArgs a = nu_args(P);
+  int gc = std::min(kGC, P->npair);
+  while (gc > 1 && spread_smem<T>(P, gc, WT) > kSmemCap) --gc;
+  const int nch = (P->npair + gc - 1) / gc;
+  for (int ch = 0; ch < nch; ++ch) {
+    a.g0 = ch * gc;
+    a.gc = std::min(gc, P->npair - a.g0);
+    hipLaunchKernelGGL((spread_kernel<T, D, WT>), dim3((unsigned)P->n_bins), dim3(kThreads),
+                       spread_smem<T>(P, a.gc, WT), P->stream, a, xs, P->cell.as<int>(),
+                       P->frac.as<T>(), P->spn.as<double>(), P->pref.as<double>(),
+                       P->bin_start.as<int>(), P->nodes_d.as<double>(), P->bary_d.as<double>(),
+                       P->gridA.as<typename V2<T>::type>());
+    GP_CHECK_LAUNCH();
+  }
+}
+
+template <typename T, int D, int WT>
+void launch_interp(Plan* P, int64_t n, const DevBuf& cell, const DevBuf& frac, const DevBuf& spn,
+                   const DevBuf& pref, const DevBuf& bin_start, const double* xs, double* ys,
+                   int add_noise) {
+  PhaseScope ps(P, PH_INTERP);
+  NuArgs a = nu_args(P);
+  a.n = n;
+  a.add_noise = add_noise;
+  int gc = std::min(kGC, P->npair);
+  while (gc > 1 && interp_smem<T>(P, gc, WT) > kSmemCap) --gc;
+  const int nch = (P->npair + gc - 1) / gc;
+  for (int ch = 0; ch < nch; ++ch) {
+    a.g0 = ch * gc;
+    a.gc = std::min(gc, P->npair - a.g0);
+    a.first_chunk = ch == 0;
+    // the 1-D four-step inverse leaves the grid in C (see fft_all)
+    const DevBuf& g = P->fourstep ? P->gridC : P->gridA;
+    hipLaunchKernelGGL((interp_kernel<T, D, WT>), dim3((unsigned)P->n_bins), dim3(kThreads),
+                       interp_smem<T>(P, a.gc, WT), P->stream, a,
+                       g.as<typename V2<T>::type>(), cell.as<int>(), frac.as<T>(),
+                       spn.as<double>(), pref.as<double>(), bin_start.as<int>(),
+                       P->nodes_d.as<double>(), P->bary_d.as<double>(), xs, ys);
+    GP_CHECK_LAUNCH();
+  }
+}
+
+template <typename T>
+void spread_dispatch(Plan* P, const double* xs) {
+  const int WT = wt_for(P->w);
+  if (P->d == 1) WT == 8 ? launch_spread<T, 1, 8>(P, xs) : launch_spread<T, 1, 16>(P, xs);
+  else if (P->d == 2) WT == 8 ? launch_spread<T, 2, 8>(P, xs) : launch_spread<T, 2, 16>(P, xs);
+  else WT == 8 ? launch_spread<T, 3, 8>(P, xs) : launch_spread<T, 3, 16>(P, xs);
+}
+
+template <typename T>
+void interp_dispatch(Plan* P, int64_t n, const DevBuf& cell, const DevBuf& frac, const DevBuf& spn,
+                     const DevBuf& pref, const DevBuf& bs, const double* xs, double* ys,
+                     int add_noise) {
+  const int WT = wt_for(P->w);
+#define GP_I(DD, W) launch_interp<T, DD, W>(P, n, cell, frac, spn, pref, bs, xs, ys, add_noise)
+  if (P->d == 1) { if (WT == 8) GP_I(1, 8); else GP_I(1, 16); }
+  else if (P->d == 2) { if (WT == 8) GP_I(2, 8); else GP_I(2, 16); }
+  else { if (WT == 8) GP_I(3, 8); else GP_I(3, 16); }
+#undef GP_I
+}
+
+template <typename T, int NK>
+void launch_mode_nk(Plan* P) {
+  PhaseScope ps(P, PH_MODE);
+  ModeArgs a;
+  a.d = P->d;
+  a.M = P->M;
+  a.mc = P->mcount;
+  a.F = 1;
+  for (int r = 0; r < P->d; ++r) a.F *= a.mc;
+  a.nk = P->nk;
+  a.npair = P->npair;
+  a.nt = P->nt_eff;
+  a.fourstep = P->fourstep;
+  a.nf = P->nf[0];
+  a.L1 = P->L1;
+  a.L2 = P->L2;
+  a.pair_stride = P->fourstep ? P->nf[0] : a.F;
+  const int64_t half = (a.F + 1) / 2;
+  hipLaunchKernelGGL((mode_kernel<T, NK>), dim3((unsigned)((half + kThreads - 1) / kThreads)),
+                     dim3(kThreads), 0, P->stream, a, P->gridC.as<typename V2<T>::type>(),
+                     P->gtab.as<T>(), P->etab.as<T>(), P->vtd.as<T>(), P->dec.as<T>());
+  GP_CHECK_LAUNCH();
+}
+
+template <typename T>
+void launch_mode(Plan* P) {
+  const int nk2 = 2 * P->npair;
+  switch (nk2) {
+#define GP_M(N) case N: launch_mode_nk<T, N>(P); break;
+    GP_M(2) GP_M(4) GP_M(6) GP_M(8) GP_M(10) GP_M(12) GP_M(14) GP_M(16) GP_M(18) GP_M(20)
+    GP_M(22) GP_M(24) GP_M(26) GP_M(28) GP_M(30) GP_M(32) GP_M(34) GP_M(36) GP_M(38) GP_M(40)
+    GP_M(42) GP_M(44) GP_M(46) GP_M(48)
+#undef GP_M
+    default:
+      throw Error{GP_EUNSUPPORTED, "too many Chebyshev nodes"};
+  }
+}
+
+// Forward (sign -1) FFT of every grid pair: active box -> truncated modes.
+// Inverse (sign +1): truncated modes -> active box.
+void fft_all(Plan* P, int sign) {
+  const int fp64 = P->precision == GP_FP64;
+  const int64_t G = P->npair, mc = P->mcount;
+  const int d = P->d;
+  const int nf = P->nf[0];
+  hipStream_t s = P->stream;
+  void* A = P->gridA.p;
+  void* B = P->gridB.p;
+  void* B2 = P->gridB2.p;
+  void* C = P->gridC.p;
+  FftPass q;
+  q.sign = sign;
+  // phase of a pass over dimension r
+  auto run = [&](int r, const FftPass& ps_, const void* in, void* out, const void* twp) {
+    PhaseScope sc(P, sign < 0 ? PH_FFT_FWD0 + r : PH_FFT_INV2 + (2 - r));
+    fft_pass(fp64, ps_, in, out, twp, s);
+  };
+  if (d == 1 && P->fourstep) {
+    const int L1 = P->L1, L2 = P->L2;
+    FftPass y;  // over l2 (stride L1)
+    y.L = L2; y.n_outer = G; y.inner = L1; y.in_os = nf; y.out_os = nf;
+    y.n_in = L2; y.in_start = 0; y.n_out = L2; y.out_start = 0; y.sign = sign;
+    FftPass x;  // over l1 (contiguous), four-step twiddle
+    x.L = L1; x.n_outer = G * L2; x.inner = 1; x.in_os = L1; x.out_os = L1;
+    x.n_in = L1; x.in_start = 0; x.n_out = L1; x.out_start = 0; x.sign = sign;
+    x.tw4 = P->tw4.p; x.L4 = nf;
+    if (sign < 0) {
+      run(1, y, A, B, P->tw[1].p);
+      x.tw4_at_load = 1;
+      run(0, x, B, C, P->tw[0].p);
+    } else {
+      // the inverse result goes to C, not A: A keeps zeros outside the active
+      // box (the spread writes only inside it) for the next forward pass
+      x.tw4_at_load = 0;
+      run(0, x, C, B, P->tw[0].p);
+      run(1, y, B, C, P->tw[1].p);
+    }
+    return;
+  }
+  const void* tw = P->tw[0].p;
+  if (d == 1) {
+    q.L = nf; q.n_outer = G; q.inner = 1;
+    if (sign < 0) {
+      q.in_os = P->na[0]; q.n_in = P->na[0]; q.in_start = P->lo[0];
+      q.out_os = mc; q.n_out = (int)mc; q.out_start = (int)-P->M;
+      run(0, q, A, C, tw);
+    } else {
+      q.in_os = mc; q.n_in = (int)mc; q.in_start = (int)-P->M;
+      q.out_os = P->na[0]; q.n_out = P->na[0]; q.out_start = P->lo[0];
+      run(0, q, C, A, tw);
+    }
+    return;
+  }
+  // dimension-0 pass (contiguous) between A [.., na0] and B [.., mc]
+  FftPass x;
+  x.L = nf; x.inner = 1; x.sign = sign;
+  x.n_outer = G * P->na[1] * (d > 2 ? P->na[2] : 1);
+  // dimension-1 pass between B [G][na2][na1][mc] and B2/C [G][na2][mc][mc]
+  FftPass y;
+  y.L = nf; y.inner = mc; y.sign = sign;
+  y.n_outer = G * (d > 2 ? P->na[2] : 1);
+  if (sign < 0) {
+    x.in_os = P->na[0]; x.n_in = P->na[0]; x.in_start = P->lo[0];
+    x.out_os = mc; x.n_out = (int)mc; x.out_start = (int)-P->M;
+    run(0, x, A, B, tw);
+    y.in_os = P->na[1] * mc; y.n_in = P->na[1]; y.in_start = P->lo[1];
+    y.out_os = mc * mc; y.n_out = (int)mc; y.out_start = (int)-P->M;
+    if (d == 2) {
+      run(1, y, B, C, tw);
+    } else {
+      run(1, y, B, B2, tw);
+      FftPass z;
+      z.L = nf; z.inner = mc * mc; z.sign = sign; z.n_outer = G;
+      z.in_os = P->na[2] * mc * mc; z.n_in = P->na[2]; z.in_start = P->lo[2];
+      z.out_os = mc * mc * mc; z.n_out = (int)mc; z.out_start = (int)-P->M;
+      run(2, z, B2, C, tw);
+    }
+  } else {
+    if (d == 3) {
+      FftPass z;
+      z.L = nf; z.inner = mc * mc; z.sign = sign; z.n_outer = G;
+      z.in_os = mc * mc * mc; z.n_in = (int)mc; z.in_start = (int)-P->M;
+      z.out_os = P->na[2] * mc * mc; z.n_out = P->na[2]; z.out_start = P->lo[2];
+      run(2, z, C, B2, tw);
+    }
+    y.in_os = mc * mc; y.n_in = (int)mc; y.in_start = (int)-P->M;
+    y.out_os = P->na[1] * mc; y.n_out = P->na[1]; y.out_start = P->lo[1];
+    run(1, y, d == 2 ? C : B2, B, tw);
+    x.in_os = mc; x.n_in = (int)mc; x.in_start = (int)-P->M;
+    x.out_os = P->na[0]; x.n_out = P->na[0]; x.out_start = P->lo[0];
+    run(0, x, B, A, tw);
+  }
+}
+
+template <typename T>
+void forward_and_mix(Plan* P, const double* xs) {
+  spread_dispatch<T>(P, xs);
+  fft_all(P, -1);
+  launch_mode<T>(P);
+  if (P->fourstep) {
+    const int64_t tot = (int64_t)P->nf[0] * P->npair;
+    hipLaunchKernelGGL(zero_band_kernel<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
+                       P->stream, P->gridC.as<typename V2<T>::type>(), (int64_t)P->nf[0],
+                       (int64_t)P->L1, (int64_t)P->L2, P->M, P->npair);
+    GP_CHECK_LAUNCH();
+  }
+  fft_all(P, +1);
+}
+
+}  // namespace
+
+void matvec_sorted(Plan* P, const double* xs, double* ys, int add_noise) {
+  if (P->precision == GP_FP64) {
+    forward_and_mix<double>(P, xs);
+    interp_dispatch<double>(P, P->n, P->cell, P->frac, P->spn, P->pref, P->bin_start, xs, ys,
+                            add_noise);
+  } else {
+    forward_and_mix<float>(P, xs);
+    interp_dispatch<float>(P, P->n, P->cell, P->frac, P->spn, P->pref, P->bin_start, xs, ys,
+                           add_noise);
+  }
+}
+
+void posterior_sorted(Plan* P, const double* xs, int64_t m, const double* tpts,
+                      const double* tsig, const double* tl, double* mu) {
+  DevBuf perm, cell, frac, spn, pref, bs;
+  int oob = 0;
+  build_records_into(P, m, tpts, tsig, tl, perm, cell, frac, spn, pref, bs, &oob);
+  if (oob) throw Error{GP_ERANGE, "posterior target outside the plan's box"};
+  DevBuf tmp;
+  tmp.alloc(m * sizeof(double));
+  if (P->precision == GP_FP64) {
+    forward_and_mix<double>(P, xs);
+    interp_dispatch<double>(P, m, cell, frac, spn, pref, bs, nullptr, tmp.as<double>(), 0);
+  } else {
+    forward_and_mix<float>(P, xs);
+    interp_dispatch<float>(P, m, cell, frac, spn, pref, bs, nullptr, tmp.as<double>(), 0);
+  }
+  hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, P->stream,
+                     m, perm.as<int>(), tmp.as<double>(), mu);
+  GP_CHECK_LAUNCH();
+  GP_HIP(hipStreamSynchronize(P->stream));
+}
+
+void gather_sorted(Plan* P, const double* xu, double* xs) {
+  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((P->n + 255) / 256)), dim3(256), 0, P->stream,
+                     P->n, P->perm.as<int>(), xu, xs);
+  GP_CHECK_LAUNCH();
+}
+
+void scatter_user(Plan* P, const double* xs, double* xu) {
+  hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)((P->n + 255) / 256)), dim3(256), 0,
+                     P->stream, P->n, P->perm.as<int>(), xs, xu);
+  GP_CHECK_LAUNCH();
+}
+
+}  // namespace gp

@@ -1,0 +1,698 @@
+// Plan construction: parameter choice, tables, point records and bin sort.
+//
+// The plan fixes the operator K~ of eq:Ktilde (section 3.5): the trapezoid
+// rule in t (eq:trapsum, eq:dtscheme), the Chebyshev-Lobatto grid in the width
+// (eq:chebscheme), and the Fourier grid Delta-omega {-M..M}^d (section 3.4),
+// plus the spreading window and oversampled grid that realise the two NUFFTs
+// (Appendix D).  It also sorts the points into spreading tiles so that every
+// matvec works on bin-ordered records (the CG vectors stay in that order).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+
+#include "gp_internal.h"
+
+namespace gp {
+
+static const double PI = 3.14159265358979323846264338327950288;
+
+void DevBuf::alloc(size_t b) {
+  release();
+  if (b == 0) b = 256;
+  hipError_t e = hipMalloc(&p, b);
+  if (e != hipSuccess) {
+    p = nullptr;
+    (void)hipGetLastError();
+    throw Error{GP_ENOMEM, "hipMalloc(" + std::to_string(b) + " bytes) failed: " +
+                               hipGetErrorString(e)};
+  }
+  bytes = b;
+}
+
+void DevBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+namespace {
+
+// ------------------------------------------------------------ host maths ----
+
+// Matern phi_nu(r) through its Gaussian-mixture representation eq:schoenberg2
+// with u, chi of eq:maternpres (fine trapezoid on a wide t range); used only to
+// size the aliasing margin, so a few digits suffice.  SE: exp(-r^2/2).
+double phi_of_r(double nu, double r) {
+  if (std::isinf(nu)) return std::exp(-0.5 * r * r);
+  const double tmin = -60.0 / nu - 20.0, tmax = 6.0;
+  const int nt = 6000;
+  const double dt = (tmax - tmin) / nt, lg = std::lgamma(nu);
+  double s = 0;
+  for (int j = 0; j <= nt; ++j) {
+    double t = tmin + j * dt;
+    double f = std::exp(nu * t - std::exp(t) - lg - r * r * nu / (2.0 * std::exp(t)));
+    s += (j == 0 || j == nt) ? 0.5 * f : f;
+  }
+  return s * dt;
+}
+
+// Smallest r with phi_nu(r) <= target (bisection; phi is decreasing).
+double r_at_level(double nu, double target) {
+  double lo = 0, hi = 1;
+  while (phi_of_r(nu, hi) > target && hi < 1e4) hi *= 2;
+  for (int it = 0; it < 80; ++it) {
+    double mid = 0.5 * (lo + hi);
+    (phi_of_r(nu, mid) > target ? lo : hi) = mid;
+  }
+  return hi;
+}
+
+// Fraction of the spectral mass of the stationary kernel with length ell that
+// lies outside the radius Omega (Fourier convention of Appendix D):
+// Matern density (1 + (2 pi ell w)^2/(2 nu))^-(nu + d/2), SE exp(-2 pi^2 ell^2 w^2),
+// integrated radially (w^(d-1) dw) on a logarithmic grid.
+double spectral_tail(double nu, int d, double ell, double Omega) {
+  auto dens = [&](double w) {
+    double a = 2 * PI * ell * w;
+    if (std::isinf(nu)) return std::exp(-0.5 * a * a);
+    return std::pow(1.0 + a * a / (2.0 * nu), -(nu + 0.5 * d));
+  };
+  const double s0 = std::log(1e-8 / ell), s1 = std::log(1e16 / ell);
+  const int ns = 40000;
+  const double ds = (s1 - s0) / ns, sO = std::log(Omega);
+  double tot = 0, tail = 0;
+  for (int i = 0; i <= ns; ++i) {
+    double s = s0 + i * ds, w = std::exp(s);
+    double f = dens(w) * std::pow(w, d);  // w^(d-1) dw = w^d ds
+    double c = (i == 0 || i == ns) ? 0.5 : 1.0;
+    tot += c * f;
+    if (s >= sO) tail += c * f;
+  }
+  return tail / tot;
+}
+
+// Sup over (x, sigma) of the Chebyshev interpolation error of lemma lem:interp,
+// sampled on a grid (the Lagrange basis evaluated in barycentric form).
+double cheb_interp_error(double smin, double smax, int ns) {
+  std::vector<double> sk(ns + 1), lam(ns + 1);
+  for (int k = 0; k <= ns; ++k) {
+    sk[k] = 0.5 * (std::cos(PI * k / ns) + 1.0) * (smax - smin) + smin;
+    lam[k] = ((k % 2) ? -1.0 : 1.0) * ((k == 0 || k == ns) ? 0.5 : 1.0);
+  }
+  double worst = 0;
+  const int nsg = 97, nx = 97;
+  for (int a = 0; a < nsg; ++a) {
+    double s = smin + (smax - smin) * (a + 0.5) / nsg;
+    double den = 0;
+    std::vector<double> P(ns + 1);
+    for (int k = 0; k <= ns; ++k) den += lam[k] / (s - sk[k]);
+    for (int k = 0; k <= ns; ++k) P[k] = lam[k] / (s - sk[k]) / den;
+    for (int b = 0; b < nx; ++b) {
+      double x = 6.0 * smax * b / (nx - 1);
+      double ap = 0;
+      for (int k = 0; k <= ns; ++k) ap += P[k] * std::exp(-x * x / (2 * sk[k] * sk[k]));
+      worst = std::max(worst, std::fabs(ap - std::exp(-x * x / (2 * s * s))));
+    }
+  }
+  return worst;
+}
+
+// Gauss-Legendre nodes/weights on [-1,1] (Newton on P_n).
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.resize(n);
+  w.resize(n);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(PI * (i + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      double dp = n * (z * p1 - p0) / (z * z - 1);
+      double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1, p1 = z;
+    for (int k = 2; k <= n; ++k) {
+      double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    double dp = n * (z * p1 - p0) / (z * z - 1);
+    x[i] = z;
+    w[i] = 2.0 / ((1 - z * z) * dp * dp);
+  }
+}
+
+// Fourier transform of the exponential-of-semicircle window
+// psi(z) = exp(beta (sqrt(1 - (2z/w)^2) - 1)), |z| <= w/2 (grid units), at xi.
+double es_hat(double xi, int w, double beta, const std::vector<double>& gx,
+              const std::vector<double>& gw) {
+  double s = 0;
+  for (size_t q = 0; q < gx.size(); ++q) {
+    double z = 0.5 * w * gx[q];
+    double a = 2 * z / w;
+    s += 0.5 * w * gw[q] * std::exp(beta * (std::sqrt(std::max(0.0, 1 - a * a)) - 1)) *
+         std::cos(xi * z);
+  }
+  return s;
+}
+
+// Smallest FFT length >= need that the pass kernel supports (single pass).
+int fft_len_at_least(int64_t need) {
+  int best = 0;
+  for (int a = 3; a <= 13; ++a)
+    for (int t = 1; t <= 3; t += 2) {
+      int64_t L = (int64_t)t << a;
+      if (L >= need && fft_length_supported((int)L) && (best == 0 || L < best)) best = (int)L;
+    }
+  return best;
+}
+
+// ---------------------------------------------------------- device parts ----
+
+struct RecArgs {
+  int d;
+  int64_t n;
+  double center[3], scale, dw;
+  int nf[3], lo[3], tile[3], nbins[3], na[3];
+  int w;
+};
+
+// Per point: mapped coordinate x' = (x - c) scale, fine-grid position
+// g = nf/2 + nf dw x' (so theta + pi = 2 pi g / nf with theta = 2 pi dw x'),
+// first window cell s = ceil(g - w/2), offset delta = s - g, its tile, and
+// sigma_p = l'/sqrt(2), prefactor s(x) (2/(pi l'^2))^(d/4) of eq:Wk.
+__global__ void records_kernel(RecArgs a, const double* __restrict__ pts,
+                               const double* __restrict__ sig, const double* __restrict__ l,
+                               int* __restrict__ bin_of, int* __restrict__ rank,
+                               int* __restrict__ counts, int* __restrict__ cell_tmp,
+                               double* __restrict__ frac_tmp, double* __restrict__ sp_tmp,
+                               double* __restrict__ pf_tmp, int* __restrict__ bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  int64_t bin = 0, mul = 1;
+  for (int r = 0; r < a.d; ++r) {
+    double xp = (pts[i * a.d + r] - a.center[r]) * a.scale;
+    double g = 0.5 * a.nf[r] + a.nf[r] * a.dw * xp;
+    double s = ceil(g - 0.5 * a.w);
+    int sa = (int)s - a.lo[r];
+    if (!(sa >= 0 && sa + a.w <= a.na[r])) {
+      atomicOr(bad, 1);
+      sa = sa < 0 ? 0 : (sa + a.w > a.na[r] ? a.na[r] - a.w : sa);
+    }
+    cell_tmp[r * a.n + i] = sa;
+    frac_tmp[r * a.n + i] = s - g;
+    bin += (int64_t)(sa / a.tile[r]) * mul;
+    mul *= a.nbins[r];
+  }
+  double lp = l[i] * a.scale;
+  sp_tmp[i] = lp * 0.70710678118654752440;
+  pf_tmp[i] = sig[i] * pow(2.0 / (3.14159265358979323846 * lp * lp), 0.25 * a.d);
+  bin_of[i] = (int)bin;
+  rank[i] = atomicAdd(&counts[bin], 1);
+}
+
+template <typename T>
+__global__ void scatter_records_kernel(int d, int64_t n, const int* __restrict__ bin_of,
+                                       const int* __restrict__ rank,
+                                       const int* __restrict__ bin_start,
+                                       const int* __restrict__ cell_tmp,
+                                       const double* __restrict__ frac_tmp,
+                                       const double* __restrict__ sp_tmp,
+                                       const double* __restrict__ pf_tmp, int* __restrict__ perm,
+                                       int* __restrict__ cell, T* __restrict__ frac,
+                                       double* __restrict__ spn, double* __restrict__ pref) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t pos = (int64_t)bin_start[bin_of[i]] + rank[i];
+  perm[pos] = (int)i;
+  for (int r = 0; r < d; ++r) {
+    cell[r * n + pos] = cell_tmp[r * n + i];
+    frac[r * n + pos] = (T)frac_tmp[r * n + i];
+  }
+  spn[pos] = sp_tmp[i];
+  pref[pos] = pf_tmp[i];
+}
+
+}  // namespace
+
+// Sort a point set into the plan's tiles and build its records (used for the
+// training points at plan time and for posterior targets).
+struct Records;  // fwd (defined in nufft.hip via Plan buffers)
+
+void build_records_into(Plan* P, int64_t n, const double* pts, const double* sig,
+                        const double* l, DevBuf& perm, DevBuf& cell, DevBuf& frac, DevBuf& spn,
+                        DevBuf& pref, DevBuf& bin_start, int* out_of_box) {
+  hipStream_t s = P->stream;
+  const int d = P->d;
+  RecArgs a;
+  a.d = d;
+  a.n = n;
+  for (int r = 0; r < 3; ++r) {
+    a.center[r] = P->center[r];
+    a.nf[r] = P->nf[r];
+    a.lo[r] = P->lo[r];
+    a.tile[r] = P->tile[r];
+    a.nbins[r] = P->nbins[r];
+    a.na[r] = P->na[r];
+  }
+  a.scale = P->scale;
+  a.dw = P->dw;
+  a.w = P->w;
+  const size_t tsz = P->precision == GP_FP64 ? sizeof(double) : sizeof(float);
+  DevBuf bin_of, rank, counts, cell_tmp, frac_tmp, sp_tmp, pf_tmp, bad;
+  bin_of.alloc(n * sizeof(int));
+  rank.alloc(n * sizeof(int));
+  counts.alloc((P->n_bins + 1) * sizeof(int));
+  cell_tmp.alloc(n * d * sizeof(int));
+  frac_tmp.alloc(n * d * sizeof(double));
+  sp_tmp.alloc(n * sizeof(double));
+  pf_tmp.alloc(n * sizeof(double));
+  bad.alloc(sizeof(int));
+  GP_HIP(hipMemsetAsync(counts.p, 0, (P->n_bins + 1) * sizeof(int), s));
+  GP_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
+  const int bs = 256;
+  const unsigned nb = (unsigned)((n + bs - 1) / bs);
+  hipLaunchKernelGGL(records_kernel, dim3(nb), dim3(bs), 0, s, a, pts, sig, l, bin_of.as<int>(),
+                     rank.as<int>(), counts.as<int>(), cell_tmp.as<int>(),
+                     frac_tmp.as<double>(), sp_tmp.as<double>(), pf_tmp.as<double>(),
+                     bad.as<int>());
+  GP_CHECK_LAUNCH();
+  std::vector<int> hc(P->n_bins + 1);
+  int hbad = 0;
+  GP_HIP(hipMemcpyAsync(hc.data(), counts.p, P->n_bins * sizeof(int), hipMemcpyDeviceToHost, s));
+  GP_HIP(hipMemcpyAsync(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  GP_HIP(hipStreamSynchronize(s));
+  if (out_of_box) *out_of_box = hbad;
+  std::vector<int> start(P->n_bins + 1);
+  int64_t acc = 0;
+  for (int64_t b = 0; b < P->n_bins; ++b) {
+    start[b] = (int)acc;
+    acc += hc[b];
+  }
+  start[P->n_bins] = (int)acc;
+  perm.alloc(n * sizeof(int));
+  cell.alloc(n * d * sizeof(int));
+  frac.alloc(n * d * tsz);
+  spn.alloc(n * sizeof(double));
+  pref.alloc(n * sizeof(double));
+  bin_start.alloc((P->n_bins + 1) * sizeof(int));
+  GP_HIP(hipMemcpyAsync(bin_start.p, start.data(), (P->n_bins + 1) * sizeof(int),
+                        hipMemcpyHostToDevice, s));
+  if (P->precision == GP_FP64)
+    hipLaunchKernelGGL(scatter_records_kernel<double>, dim3(nb), dim3(bs), 0, s, d, n,
+                       bin_of.as<int>(), rank.as<int>(), bin_start.as<int>(), cell_tmp.as<int>(),
+                       frac_tmp.as<double>(), sp_tmp.as<double>(), pf_tmp.as<double>(),
+                       perm.as<int>(), cell.as<int>(), frac.as<double>(), spn.as<double>(),
+                       pref.as<double>());
+  else
+    hipLaunchKernelGGL(scatter_records_kernel<float>, dim3(nb), dim3(bs), 0, s, d, n,
+                       bin_of.as<int>(), rank.as<int>(), bin_start.as<int>(), cell_tmp.as<int>(),
+                       frac_tmp.as<double>(), sp_tmp.as<double>(), pf_tmp.as<double>(),
+                       perm.as<int>(), cell.as<int>(), frac.as<float>(), spn.as<double>(),
+                       pref.as<double>());
+  GP_CHECK_LAUNCH();
+  GP_HIP(hipStreamSynchronize(s));
+}
+
+// ------------------------------------------------------------ build_plan ----
+
+int build_plan(int d, int64_t n, const double* pts, const double* sigma, const double* l,
+               double nu, double eta, double tol, const gp_opts* opts_in, Plan* P,
+               bool query_only, size_t* bytes_out) {
+  gp_opts opts;
+  if (opts_in)
+    opts = *opts_in;
+  else
+    gp_opts_init(&opts);
+  if (d < 1 || d > 3) throw Error{GP_EINVAL, "d must be 1, 2 or 3"};
+  if (n < 1 || n > (int64_t)std::numeric_limits<int>::max() / 4)
+    throw Error{GP_EINVAL, "n must be in [1, 2^29)"};
+  if (!pts || !sigma || !l) throw Error{GP_EINVAL, "null input pointer"};
+  if (!(nu > 0)) throw Error{GP_EDOMAIN, "nu must be > 0"};
+  if (!(eta >= 0) || !std::isfinite(eta)) throw Error{GP_EDOMAIN, "eta must be finite and >= 0"};
+  if (!(tol > 0) || !(tol < 1)) throw Error{GP_EDOMAIN, "tol must be in (0, 1)"};
+  if (opts.precision != GP_FP64 && opts.precision != GP_FP32_BULK)
+    throw Error{GP_EINVAL, "unknown precision"};
+
+  P->d = d;
+  P->n = n;
+  P->precision = opts.precision;
+  P->nu = nu;
+  P->eta = eta;
+  P->se = std::isinf(nu);
+  P->stream = static_cast<hipStream_t>(opts.stream);
+  hipStream_t s = P->stream;
+
+  // ---- host copies for validation and ranges
+  std::vector<double> hx(n * d), hs(n), hl(n);
+  GP_HIP(hipMemcpyAsync(hx.data(), pts, n * d * sizeof(double), hipMemcpyDeviceToHost, s));
+  GP_HIP(hipMemcpyAsync(hs.data(), sigma, n * sizeof(double), hipMemcpyDeviceToHost, s));
+  GP_HIP(hipMemcpyAsync(hl.data(), l, n * sizeof(double), hipMemcpyDeviceToHost, s));
+  GP_HIP(hipStreamSynchronize(s));
+  double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  for (int r = 0; r < d; ++r) {
+    lo[r] = std::numeric_limits<double>::infinity();
+    hi[r] = -lo[r];
+  }
+  double lmin = std::numeric_limits<double>::infinity(), lmax = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    for (int r = 0; r < d; ++r) {
+      double v = hx[i * d + r];
+      if (!std::isfinite(v)) throw Error{GP_EDOMAIN, "non-finite point coordinate"};
+      lo[r] = std::min(lo[r], v);
+      hi[r] = std::max(hi[r], v);
+    }
+    if (!(hs[i] > 0) || !std::isfinite(hs[i])) throw Error{GP_EDOMAIN, "sigma must be finite and > 0"};
+    if (!(hl[i] > 0) || !std::isfinite(hl[i])) throw Error{GP_EDOMAIN, "l must be finite and > 0"};
+    lmin = std::min(lmin, hl[i]);
+    lmax = std::max(lmax, hl[i]);
+  }
+  if (opts.use_box) {
+    for (int r = 0; r < d; ++r) {
+      if (!(opts.box_lo[r] <= lo[r] && opts.box_hi[r] >= hi[r]))
+        throw Error{GP_ERANGE, "points outside gp_opts box"};
+      lo[r] = opts.box_lo[r];
+      hi[r] = opts.box_hi[r];
+    }
+  }
+  if (opts.l_lo > 0) lmin = std::min(lmin, opts.l_lo);
+  if (opts.l_hi > 0) lmax = std::max(lmax, opts.l_hi);
+
+  // ---- isotropic map onto [-1,1]^d (section 5 assumes the points lie there)
+  double ext = 0;
+  for (int r = 0; r < d; ++r) {
+    P->center[r] = 0.5 * (lo[r] + hi[r]);
+    ext = std::max(ext, hi[r] - lo[r]);
+  }
+  if (!(ext > 0)) ext = 2.0;
+  P->scale = 2.0 / ext;
+  P->l_range_lo = lmin;
+  P->l_range_hi = lmax;
+
+  // ---- width range (sigma_p = l'/sqrt 2) and Chebyshev degree (section 3.3)
+  const double sq2 = std::sqrt(2.0);
+  double smin = lmin * P->scale / sq2, smax = lmax * P->scale / sq2;
+  if (opts.s_min > 0 || opts.s_max > 0) {
+    if (!(opts.s_min > 0 && opts.s_max >= opts.s_min))
+      throw Error{GP_EINVAL, "s_min/s_max must both be set, 0 < s_min <= s_max"};
+    if (opts.s_min > smin * (1 + 1e-12) || opts.s_max < smax * (1 - 1e-12))
+      throw Error{GP_ERANGE, "gp_opts width range does not contain the data's"};
+    smin = opts.s_min;
+    smax = opts.s_max;
+  }
+  const double eps = tol;
+  if (opts.n_sigma >= 0) {
+    P->n_sigma = opts.n_sigma;
+  } else if (smax <= smin * (1 + 1e-13)) {
+    P->n_sigma = 0;
+  } else {
+    const double kappa = smax / smin;
+    const double target = eps / 10;
+    int nb = 1;
+    while (2 * (kappa - 1) * std::pow((kappa - 1) / (kappa + 1), nb) > target && nb < 200) ++nb;
+    int ns = 1;
+    while (ns < nb && cheb_interp_error(smin, smax, ns) > target) ++ns;
+    if (ns % 2 == 0) ++ns;  // N_sigma + 1 even: grids pack in complex pairs
+    P->n_sigma = ns;
+  }
+  if (P->n_sigma == 0) smax = smin;
+  P->s_min = smin;
+  P->s_max = smax;
+  if (P->n_sigma > 47) throw Error{GP_EUNSUPPORTED, "N_sigma > 47 not supported"};
+
+  // ---- t discretisation (section 3.2, lemma lem:dt)
+  if (P->se) {
+    P->t_min = P->t_max = 0;
+    P->n_t = 0;
+  } else if (opts.n_t >= 1) {
+    if (!(opts.t_max > opts.t_min)) throw Error{GP_EINVAL, "t_max must exceed t_min"};
+    P->t_min = opts.t_min;
+    P->t_max = opts.t_max;
+    P->n_t = opts.n_t;
+  } else {
+    const double L10 = std::log(10.0 / eps);
+    P->t_min = std::log(eps / 10.0) / nu;
+    P->t_max = std::log(2.0 * L10) + 0.5;
+    const double dt = PI * PI / L10;
+    P->n_t = (int)std::ceil((P->t_max - P->t_min) / dt);
+  }
+  P->nt_eff = P->se ? 1 : P->n_t + 1;
+
+  // ---- Fourier grid spacing: aliasing images at distance >= 1/dw - 2 see the
+  // kernel's own tail; ask phi_nu(r) <= eps/10 there for the widest length.
+  const double lpmax = lmax * P->scale, lpmin = lmin * P->scale;
+  if (opts.dw > 0) {
+    P->dw = opts.dw;
+  } else {
+    double r_eps = r_at_level(nu, eps / 10);
+    P->dw = std::min(0.45, 1.0 / (2.0 + lpmax * r_eps));
+  }
+  if (!(P->dw > 0 && P->dw < 0.5)) throw Error{GP_EINVAL, "Delta-omega must be in (0, 1/2)"};
+
+  // ---- Fourier half-width: spectral tail of the narrowest kernel <= eps
+  int64_t mcap = opts.M_cap > 0 ? opts.M_cap : (d == 1 ? (int64_t)1 << 18 : 2047);
+  if (opts.M > 0) {
+    P->M = opts.M;
+  } else {
+    double lo_O = 1e-3, hi_O = 1.0;
+    while (spectral_tail(nu, d, lpmin, hi_O) > eps && hi_O < 1e12) hi_O *= 2;
+    for (int it = 0; it < 60; ++it) {
+      double mid = std::sqrt(lo_O * hi_O);
+      (spectral_tail(nu, d, lpmin, mid) > eps ? lo_O : hi_O) = mid;
+    }
+    int64_t M = (int64_t)std::ceil(hi_O / P->dw);
+    M = std::max<int64_t>(M, 4);
+    if (M > mcap) {
+      M = mcap;
+      P->m_capped = 1;
+    }
+    P->M = M;
+  }
+  P->pred_tail = spectral_tail(nu, d, lpmin, P->M * P->dw);
+  P->mcount = 2 * P->M + 1;
+
+  // ---- spreading window (exponential of semicircle) and oversampled grid
+  double ntol = opts.nufft_tol > 0 ? opts.nufft_tol : eps;
+  if (P->precision == GP_FP32_BULK) ntol = std::max(ntol, 1e-6);
+  ntol = std::min(ntol, 1e-1);
+  P->nufft_tol = ntol;
+  P->w = (int)std::ceil(std::log10(1.0 / ntol)) + 1;
+  P->w = std::max(2, std::min(16, P->w));
+  P->beta = 2.30 * P->w;
+  const int64_t need_os = 2 * P->mcount;
+  const double margin = 0.5 * P->w + 2.0;
+  const int64_t need_wrap = (int64_t)std::ceil(margin / (0.5 - P->dw));
+  const int64_t need = std::max<int64_t>({need_os, need_wrap, 2 * (int64_t)P->w, 16});
+  int nf = fft_len_at_least(need);
+  P->fourstep = 0;
+  if (nf == 0) {
+    if (d != 1) throw Error{GP_EUNSUPPORTED, "Fourier grid too large for d >= 2 (reduce M)"};
+    // d = 1: nf = L1 * L2 with both factors single-pass lengths
+    int64_t best = 0;
+    int b1 = 0, b2 = 0;
+    for (int a1 = 3; a1 <= 13; ++a1)
+      for (int t1 = 1; t1 <= 3; t1 += 2)
+        for (int a2 = 3; a2 <= 13; ++a2)
+          for (int t2 = 1; t2 <= 3; t2 += 2) {
+            int64_t L1 = (int64_t)t1 << a1, L2 = (int64_t)t2 << a2;
+            if (!fft_length_supported((int)L1) || !fft_length_supported((int)L2)) continue;
+            int64_t L = L1 * L2;
+            if (L >= need && (best == 0 || L < best || (L == best && std::llabs(L1 - L2) < std::llabs(b1 - b2)))) {
+              best = L;
+              b1 = (int)L1;
+              b2 = (int)L2;
+            }
+          }
+    if (best == 0) throw Error{GP_EUNSUPPORTED, "Fourier grid too large"};
+    if (best > (int64_t)1 << 26) throw Error{GP_EUNSUPPORTED, "Fourier grid too large"};
+    nf = (int)best;
+    P->fourstep = 1;
+    P->L1 = b1;  // contiguous factor
+    P->L2 = b2;
+  }
+  const int tile_d[4] = {0, 256, 16, 8};
+  for (int r = 0; r < 3; ++r) {
+    if (r >= d) {
+      P->nf[r] = 1;
+      P->lo[r] = 0;
+      P->na[r] = 1;
+      P->tile[r] = 1;
+      P->nbins[r] = 1;
+      continue;
+    }
+    P->nf[r] = nf;
+    int tl = tile_d[d];
+    int a0 = (int)std::floor(0.5 * nf - nf * P->dw - 0.5 * P->w) - 1;
+    int a1 = (int)std::ceil(0.5 * nf + nf * P->dw + 0.5 * P->w) + 1;
+    a0 = std::max(a0, 0);
+    a1 = std::min(a1, nf - 1);
+    int na = a1 - a0 + 1;
+    na = ((na + tl - 1) / tl) * tl;
+    if (a0 + na > nf) a0 = nf - na;
+    if (a0 < 0) {
+      // grid smaller than a tile multiple: shrink the tile
+      tl = 1;
+      while (tl * 2 <= nf && tl < tile_d[d]) tl *= 2;
+      na = nf;
+      a0 = 0;
+      na = (na / tl) * tl;
+    }
+    P->lo[r] = a0;
+    P->na[r] = na;
+    P->tile[r] = tl;
+    P->nbins[r] = na / tl;
+  }
+  P->n_bins = (int64_t)P->nbins[0] * P->nbins[1] * P->nbins[2];
+  P->nk = P->n_sigma + 1;
+  P->npair = (P->nk + 1) / 2;
+
+  // ---- memory
+  const size_t cs = P->precision == GP_FP64 ? 16 : 8;  // complex element
+  const size_t ts = cs / 2;
+  int64_t szA = 1, szB = 1, szB2 = 0, szC = 1;
+  const int64_t mc = P->mcount;
+  if (d == 1) {
+    szA = P->fourstep ? nf : P->na[0];
+    szB = P->fourstep ? nf : mc;
+    szC = P->fourstep ? nf : mc;
+  } else if (d == 2) {
+    szA = (int64_t)P->na[0] * P->na[1];
+    szB = (int64_t)P->na[1] * mc;
+    szC = mc * mc;
+  } else {
+    szA = (int64_t)P->na[0] * P->na[1] * P->na[2];
+    szB = (int64_t)P->na[2] * P->na[1] * mc;
+    szB2 = (int64_t)P->na[2] * mc * mc;
+    szC = mc * mc * mc;
+  }
+  const int64_t G = P->npair;
+  size_t bytes = 0;
+  bytes += (size_t)G * (szA + szB + szB2 + szC) * cs;
+  bytes += (size_t)n * (sizeof(int) * (1 + d) + ts * d + 2 * sizeof(double));
+  bytes += (size_t)(P->n_bins + 1) * sizeof(int);
+  bytes += (size_t)P->nt_eff * P->nk * (P->M + 1) * ts * 2;
+  bytes += (size_t)n * 8 * sizeof(double);  // vectors
+  bytes += (size_t)nf * cs * 2;
+  P->device_bytes = bytes;
+  if (bytes_out) *bytes_out = bytes;
+  if (query_only) return GP_OK;
+  if (opts.max_device_bytes > 0 && bytes > opts.max_device_bytes)
+    throw Error{GP_ENOMEM, "plan needs " + std::to_string(bytes) + " device bytes, over the limit"};
+
+  // ---- host tables: sigma nodes, barycentric weights, t grid
+  P->sig_nodes.resize(P->nk);
+  P->bary.resize(P->nk);
+  for (int k = 0; k < P->nk; ++k) {
+    if (P->n_sigma == 0) {
+      P->sig_nodes[k] = smin;
+      P->bary[k] = 1;
+    } else {
+      P->sig_nodes[k] = 0.5 * (std::cos(PI * k / P->n_sigma) + 1.0) * (smax - smin) + smin;
+      P->bary[k] = ((k % 2) ? -1.0 : 1.0) * ((k == 0 || k == P->n_sigma) ? 0.5 : 1.0);
+    }
+  }
+  P->vt.resize(P->nt_eff);
+  P->chi.resize(P->nt_eff);
+  const double dwd = std::pow(P->dw, d);
+  if (P->se) {
+    P->vt[0] = dwd;
+    P->chi[0] = 1.0;
+  } else {
+    const double dt = (P->t_max - P->t_min) / P->n_t, lg = std::lgamma(nu);
+    for (int j = 0; j <= P->n_t; ++j) {
+      double t = P->t_min + (double)j / P->n_t * (P->t_max - P->t_min);
+      double u = std::exp(nu * t - std::exp(t) - lg);          // eq:maternpres
+      double ch = std::exp(0.5 * t) / std::sqrt(nu);
+      double v = std::pow(ch, -(double)d) * u;                  // eq:v
+      P->vt[j] = dwd * v * dt * ((j == 0 || j == P->n_t) ? 0.5 : 1.0);  // eq:trapsum
+      P->chi[j] = ch;
+    }
+  }
+
+  // Fourier multipliers of G_{k,t_j} (eq:Gkt) on the grid, separated by
+  // dimension: G^_{kj}[n] = (2 pi s^2)^(d/2) prod_r exp(-2 pi^2 s^2 dw^2 n_r^2),
+  // s = sigma_k chi_j.  gtab carries the constant and dimension 0, etab the rest.
+  const int64_t M1 = P->M + 1;
+  std::vector<double> g0((size_t)P->nt_eff * P->nk * M1), e1((size_t)P->nt_eff * P->nk * M1);
+  for (int j = 0; j < P->nt_eff; ++j)
+    for (int k = 0; k < P->nk; ++k) {
+      double s2 = P->sig_nodes[k] * P->sig_nodes[k] * P->chi[j] * P->chi[j];
+      double cst = std::pow(2 * PI * s2, 0.5 * d);
+      double tau = 2 * PI * PI * s2 * P->dw * P->dw;
+      for (int64_t m = 0; m < M1; ++m) {
+        double e = std::exp(-tau * (double)m * (double)m);
+        g0[((size_t)j * P->nk + k) * M1 + m] = cst * e;
+        e1[((size_t)j * P->nk + k) * M1 + m] = e;
+      }
+    }
+  // deconvolution 1/psi^(2 pi n / nf) of the window (Appendix D NUFFTs)
+  std::vector<double> gx, gw;
+  gauss_legendre(120 + 8 * P->w, gx, gw);
+  std::vector<double> dec((size_t)d * M1);
+  for (int r = 0; r < d; ++r)
+    for (int64_t m = 0; m < M1; ++m)
+      dec[r * M1 + m] = 1.0 / es_hat(2 * PI * (double)m / P->nf[r], P->w, P->beta, gx, gw);
+
+  auto upload = [&](DevBuf& buf, const std::vector<double>& v) {
+    if (P->precision == GP_FP64) {
+      buf.alloc(v.size() * sizeof(double));
+      GP_HIP(hipMemcpyAsync(buf.p, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice, s));
+      GP_HIP(hipStreamSynchronize(s));
+    } else {
+      std::vector<float> f(v.begin(), v.end());
+      buf.alloc(f.size() * sizeof(float));
+      GP_HIP(hipMemcpyAsync(buf.p, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice, s));
+      GP_HIP(hipStreamSynchronize(s));
+    }
+  };
+  upload(P->gtab, g0);
+  upload(P->etab, e1);
+  upload(P->vtd, P->vt);
+  upload(P->dec, dec);
+  P->nodes_d.alloc(P->nk * sizeof(double));
+  P->bary_d.alloc(P->nk * sizeof(double));
+  GP_HIP(hipMemcpyAsync(P->nodes_d.p, P->sig_nodes.data(), P->nk * sizeof(double), hipMemcpyHostToDevice, s));
+  GP_HIP(hipMemcpyAsync(P->bary_d.p, P->bary.data(), P->nk * sizeof(double), hipMemcpyHostToDevice, s));
+
+  // FFT twiddles exp(-2 pi i k / L) for the pass lengths in use
+  auto twiddles = [&](DevBuf& buf, int L) {
+    std::vector<double> t(2 * (size_t)L);
+    for (int k = 0; k < L; ++k) {
+      long double a = -2.0L * 3.14159265358979323846264338327950288L * k / L;
+      t[2 * k] = (double)cosl(a);
+      t[2 * k + 1] = (double)sinl(a);
+    }
+    upload(buf, t);
+  };
+  if (P->fourstep) {
+    twiddles(P->tw[0], P->L1);
+    twiddles(P->tw[1], P->L2);
+    twiddles(P->tw4, nf);
+  } else {
+    twiddles(P->tw[0], nf);
+  }
+
+  // ---- points: records and bin sort
+  int oob = 0;
+  build_records_into(P, n, pts, sigma, l, P->perm, P->cell, P->frac, P->spn, P->pref,
+                     P->bin_start, &oob);
+  if (oob) throw Error{GP_EDEVICE, "internal: a point's window left the active grid"};
+
+  // ---- grids and vectors
+  P->gridA.alloc((size_t)G * szA * cs);
+  P->gridB.alloc((size_t)G * szB * cs);
+  if (szB2) P->gridB2.alloc((size_t)G * szB2 * cs);
+  P->gridC.alloc((size_t)G * szC * cs);
+  if (P->fourstep) GP_HIP(hipMemsetAsync(P->gridA.p, 0, P->gridA.bytes, s));
+  P->vec.alloc((size_t)n * 8 * sizeof(double));
+  GP_HIP(hipStreamSynchronize(s));
+  return GP_OK;
+}
+
+}  // namespace gp

@@ -1,0 +1,226 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bar (spec tolerances): relative 2-norm error of the matvec <= 1e-6 in the
+fp64 path and <= 2e-4 in the fp32-bulk path against the oracle's K~ with the
+same parameters; CG solutions within 1e-6 of the Cholesky solution.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2407_03608_amd import inputs
+from tests.gpu_common import cuda, host, oracle_params, rel, say
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-6
+FP32_TOL = 2e-4
+
+
+@pytest.fixture(scope="module")
+def gp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2407_03608_amd import gp as g
+    g.load()
+    O.build()
+    return g
+
+
+def _plan(gp, prob, tol=1e-8, precision=0, **opts):
+    return gp.Plan(cuda(prob.x), cuda(prob.sigma), cuda(prob.l), prob.nu, prob.eta, tol,
+                   precision=precision, **opts)
+
+
+def _check_matvec(gp, prob, tol=1e-8, precision=0, bar=FP64_TOL, seed=0, **opts):
+    say(f"case {prob.name} nu={prob.nu} prec={precision} opts={opts}")
+    P = _plan(gp, prob, tol=tol, precision=precision, **opts)
+    info = P.info()
+    say("  plan", {k: info[k] for k in ("n_sigma", "n_t", "dw", "M", "nf", "w", "na", "tile", "n_pairs")})
+    a = np.random.default_rng(seed).standard_normal(prob.n)
+    got = host(P.matvec(cuda(a)))
+    ref = O.ktilde_matvec(oracle_params(info), prob.x, prob.sigma, prob.l, a)
+    e = rel(got, ref)
+    say(f"  rel err vs oracle K~ = {e:.3e}")
+    assert e <= bar, e
+    return P, info, a, got, ref
+
+
+@pytest.mark.parametrize("d,n,M,nu", [
+    (1, 300, 150, 1.5),
+    (1, 257, 60, 0.5),
+    (2, 700, 24, 1.5),
+    (2, 513, 20, 0.5),
+    (2, 400, 18, math.inf),
+    (3, 300, 8, 2.5),
+    (3, 257, 7, math.inf),
+])
+def test_matvec_fp64_vs_oracle(gp, d, n, M, nu):
+    prob = inputs.random_small(d, n, seed=10 * d + n % 7, nu=nu, lmin=0.08, lmax=0.2)
+    _check_matvec(gp, prob, tol=1e-9, M=M)
+
+
+@pytest.mark.parametrize("d,n,M", [(1, 300, 150), (2, 600, 24), (3, 300, 8)])
+def test_matvec_fp32_vs_oracle(gp, d, n, M):
+    prob = inputs.random_small(d, n, seed=3 + d, nu=1.5, lmin=0.08, lmax=0.2)
+    _check_matvec(gp, prob, tol=1e-4, precision=1, bar=FP32_TOL, M=M)
+
+
+def test_matvec_fourstep_1d(gp):
+    """d = 1 with an oversampled grid longer than one FFT pass (four-step)."""
+    prob = inputs.random_small(1, 200, seed=5, nu=1.5, lmin=0.01, lmax=0.03)
+    P, info, *_ = _check_matvec(gp, prob, tol=1e-9, M=2600)
+    assert info["nf"][0] > 8192
+
+
+@pytest.mark.parametrize("d,M,prec", [(1, 2600, 0), (1, 100, 1), (2, 20, 0), (3, 7, 1)])
+def test_repeated_matvecs_are_independent(gp, d, M, prec):
+    """A matvec leaves no state behind: K(a), K(b), K(a) gives K(a) twice."""
+    prob = inputs.random_small(d, 300, seed=40 + d, nu=1.5, lmin=0.01 if M > 1000 else 0.08,
+                               lmax=0.03 if M > 1000 else 0.2)
+    P = _plan(gp, prob, tol=1e-9 if prec == 0 else 1e-4, precision=prec, M=M)
+    rng = np.random.default_rng(7)
+    a, b = rng.standard_normal(prob.n), rng.standard_normal(prob.n)
+    k1 = host(P.matvec(cuda(a)))
+    host(P.matvec(cuda(b)))
+    k3 = host(P.matvec(cuda(a)))
+    assert rel(k3, k1) < (1e-12 if prec == 0 else 1e-5)
+
+
+def test_matvec_stationary_and_constant_scales(gp):
+    prob = inputs.random_small(2, 300, seed=8, nu=2.5, constant_scales=True)
+    P, info, a, got, ref = _check_matvec(gp, prob, tol=1e-9, M=24)
+    assert info["n_sigma"] == 0
+
+
+def test_matvec_clustered_points_fill_bins_beyond_one_batch(gp):
+    """Hundreds of points inside one spreading tile (point batches of 64)."""
+    rng = np.random.default_rng(4)
+    base = inputs.random_small(2, 600, seed=4, nu=1.5, lmin=0.1, lmax=0.2)
+    x = base.x.copy()
+    x[:450] = 0.5 + 0.004 * rng.standard_normal((450, 2))
+    prob = inputs.Problem("clustered", 2, x, base.sigma, base.l, 1.5, 0.1, base.y)
+    _check_matvec(gp, prob, tol=1e-9, M=20)
+
+
+def test_matvec_single_point_and_two_points(gp):
+    prob = inputs.random_small(2, 1, seed=1, nu=1.5)
+    P = _plan(gp, prob, tol=1e-8, M=12)
+    a = np.array([0.7])
+    got = host(P.matvec(cuda(a)))
+    ref = O.ktilde_matvec(oracle_params(P.info()), prob.x, prob.sigma, prob.l, a)
+    assert rel(got, ref) < FP64_TOL
+    prob2 = inputs.random_small(3, 2, seed=2, nu=0.5)
+    _check_matvec(gp, prob2, tol=1e-8, M=6)
+
+
+def test_add_noise_and_linearity(gp):
+    prob = inputs.random_small(2, 400, seed=12, nu=1.5)
+    P = _plan(gp, prob, tol=1e-9, M=20)
+    rng = np.random.default_rng(1)
+    u, v = rng.standard_normal(prob.n), rng.standard_normal(prob.n)
+    ku = host(P.matvec(cuda(u)))
+    kv = host(P.matvec(cuda(v)))
+    kuv = host(P.matvec(cuda(2.0 * u - 3.0 * v)))
+    assert rel(kuv, 2 * ku - 3 * kv) < 1e-12
+    kn = host(P.matvec(cuda(u), add_noise=True))
+    assert rel(kn, ku + prob.eta ** 2 * u) < 1e-13
+    # symmetry <u, K v> = <K u, v>: type 2 is the adjoint of type 1 (Appendix D)
+    assert abs(u @ kv - ku @ v) < 1e-10 * abs(u @ kv)
+
+
+def test_cg_matches_cholesky_of_ktilde(gp):
+    prob = inputs.random_small(2, 300, seed=21, nu=1.5, lmin=0.1, lmax=0.2, eta=0.3)
+    P = _plan(gp, prob, tol=1e-10, M=22)
+    info = P.info()
+    Kt = O.ktilde_entries(oracle_params(info), prob.x, prob.sigma, prob.l)
+    A = Kt + prob.eta ** 2 * np.eye(prob.n)
+    ref = O.chol_solve(O.cholesky(A), prob.y)
+    a, ci = P.cg_solve(cuda(prob.y), tol=1e-11, max_iter=5000)
+    say("  cg", ci)
+    assert ci["status"] == 0
+    assert rel(host(a), ref) <= 1e-6
+
+
+def test_cg_replacement_and_x0(gp):
+    prob = inputs.random_small(1, 300, seed=2, nu=2.5, eta=0.2)
+    P = _plan(gp, prob, tol=1e-10, M=200)
+    a1, i1 = P.cg_solve(cuda(prob.y), tol=1e-10, max_iter=4000)
+    a2, i2 = P.cg_solve(cuda(prob.y), tol=1e-10, max_iter=4000, replace_every=10)
+    assert i1["status"] == 0 and i2["status"] == 0
+    assert rel(host(a2), host(a1)) < 1e-8
+    a3, i3 = P.cg_solve(cuda(prob.y), tol=1e-10, max_iter=4000, x0=a1)
+    assert i3["iters"] <= 2
+    assert P.residual(cuda(prob.y), a1) < 1e-8
+
+
+def test_cg_max_iter_reports_noconv(gp):
+    prob = inputs.random_small(2, 300, seed=3, nu=1.5, eta=0.01)
+    P = _plan(gp, prob, tol=1e-8, M=16)
+    a, ci = P.cg_solve(cuda(prob.y), tol=1e-14, max_iter=3)
+    assert ci["status"] == gp.GP_ENOCONV and ci["iters"] == 3
+    assert np.all(np.isfinite(host(a)))
+
+
+def test_matern_1d_config_against_exact_kernel(gp):
+    """d=1, N=2000, nu=3/2, tol 1e-8: matvec within 1e-6 of the exact K and the
+    CG solution (rel. residual 1e-8) within 1e-6 of the exact Cholesky solution."""
+    prob = inputs.matern_1d()
+    P = _plan(gp, prob, tol=1e-8)
+    info = P.info()
+    say("  c1 plan", {k: info[k] for k in ("n_sigma", "n_t", "dw", "M", "nf", "w", "pred_tail", "m_capped")})
+    a = np.random.default_rng(0).standard_normal(prob.n)
+    got = host(P.matvec(cuda(a)))
+    ex = O.exact_matvec(prob.x, prob.sigma, prob.l, prob.nu, a)
+    e = rel(got, ex)
+    say(f"  matvec vs exact K: {e:.3e}")
+    assert e <= FP64_TOL
+    al, ci = P.cg_solve(cuda(prob.y), tol=1e-8, max_iter=20000)
+    say("  cg", ci)
+    ref = O.gpr_solve_exact(prob.x, prob.sigma, prob.l, prob.nu, prob.eta, prob.y)
+    es = rel(host(al), ref)
+    say(f"  solution vs exact Cholesky: {es:.3e}")
+    assert ci["status"] == 0 and es <= 1e-6
+
+
+def test_posterior_mean(gp):
+    prob = inputs.random_small(2, 300, seed=31, nu=1.5, eta=0.3)
+    P = _plan(gp, prob, tol=1e-10, M=20)
+    al, ci = P.cg_solve(cuda(prob.y), tol=1e-12, max_iter=5000)
+    alh = host(al)
+    # at the training points mu = K~ alpha = y - eta^2 alpha (eq:postmean with eq:gprsolve)
+    mu_tr = host(P.posterior_mean(al, cuda(prob.x), cuda(prob.sigma), cuda(prob.l)))
+    assert rel(mu_tr, prob.y - prob.eta ** 2 * alh) < 1e-8
+    # at new targets inside the box and length range: the oracle's K~ rows
+    rng = np.random.default_rng(2)
+    m = 40
+    xt = rng.uniform(prob.x.min(0), prob.x.max(0), size=(m, 2))
+    lt = rng.uniform(prob.l.min(), prob.l.max(), size=m)
+    st = rng.uniform(0.5, 1.5, size=m)
+    mu = host(P.posterior_mean(al, cuda(xt), cuda(st), cuda(lt)))
+    Kt = O.ktilde_entries(oracle_params(P.info()), xt, st, lt, prob.x, prob.sigma, prob.l)
+    assert rel(mu, Kt @ alh) < FP64_TOL
+
+
+def test_errors_are_reported(gp):
+    prob = inputs.random_small(2, 50, seed=1)
+    bad = prob.sigma.copy()
+    bad[3] = 0.0
+    with pytest.raises(gp.GpError) as e:
+        gp.Plan(cuda(prob.x), cuda(bad), cuda(prob.l), 1.5, 0.1, 1e-6)
+    assert e.value.code == gp.GP_EDOMAIN
+    badx = prob.x.copy()
+    badx[0, 0] = np.nan
+    with pytest.raises(gp.GpError) as e:
+        gp.Plan(cuda(badx), cuda(prob.sigma), cuda(prob.l), 1.5, 0.1, 1e-6)
+    assert e.value.code == gp.GP_EDOMAIN
+    P = _plan(gp, prob, tol=1e-6, M=10)
+    al = cuda(np.ones(prob.n))
+    with pytest.raises(gp.GpError) as e:
+        P.posterior_mean(al, cuda(np.array([[5.0, 0.5]])), cuda([1.0]), cuda([0.15]))
+    assert e.value.code == gp.GP_ERANGE
+    with pytest.raises(gp.GpError) as e:
+        P.posterior_mean(al, cuda(np.array([[0.5, 0.5]])), cuda([1.0]), cuda([10.0]))
+    assert e.value.code == gp.GP_ERANGE
