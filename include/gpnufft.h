@@ -74,6 +74,9 @@ typedef struct {
   double box_lo[3], box_hi[3];
   double l_lo, l_hi;        /* widen the length-scale range (posterior targets); 0 = unused */
   size_t max_device_bytes;  /* admission limit for the plan's device memory; 0 = none */
+  int step3;                /* step 3 of section 4.2 (rem:step3): 0 = precomputed tensor
+                               A_k'k, stored once per distinct |n|^2 (default); 1 = direct
+                               sum over the t nodes at every mode */
   void* stream;             /* hipStream_t; NULL = null stream */
 } gp_opts;
 
@@ -101,6 +104,8 @@ typedef struct {
   size_t device_bytes;      /* device memory held by the plan */
   double pred_tail;         /* predicted spectral-tail error of the Fourier box, relative */
   int m_capped;             /* 1 if M was limited by M_cap */
+  int step3;                /* variant of step 3 in use (see gp_opts.step3) */
+  int64_t a_rows;           /* rows of the precomputed A table (distinct |n|^2) */
 } gp_plan_params;
 
 typedef struct {

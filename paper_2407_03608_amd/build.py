@@ -14,7 +14,16 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgpnufft.so")
-SOURCES = ["gp_fft.hip", "gp_plan.hip", "gp_nufft.hip", "gp_cg.hip", "gp_capi.hip"]
+# (source, object, extra flags): gp_mode.hip is built once per precision
+SOURCES = [
+    ("gp_fft.hip", "gp_fft.o", []),
+    ("gp_plan.hip", "gp_plan.o", []),
+    ("gp_nufft.hip", "gp_nufft.o", []),
+    ("gp_mode.hip", "gp_mode64.o", ["-DGP_MODE_FP64=1"]),
+    ("gp_mode.hip", "gp_mode32.o", ["-DGP_MODE_FP64=0"]),
+    ("gp_cg.hip", "gp_cg.o", []),
+    ("gp_capi.hip", "gp_capi.o", []),
+]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("GP_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
@@ -28,9 +37,10 @@ FLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(job) -> str:
+    src, objname, extra = job
+    obj = os.path.join(OBJ, objname)
+    cmd = [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

@@ -161,6 +161,8 @@ int gp_plan_info(gp_plan_t h, gp_plan_params* o) {
     o->device_bytes = P.device_bytes;
     o->pred_tail = P.pred_tail;
     o->m_capped = P.m_capped;
+    o->step3 = P.step3;
+    o->a_rows = P.a_rows;
     return GP_OK;
   });
 }

@@ -118,6 +118,11 @@ struct Plan {
   DevBuf gtab;                // T [nt][nk][M+1]: C_kj * exp(-tau_kj n^2) for dim 0
   DevBuf etab;                // T [nt][nk][M+1]: exp(-tau_kj n^2) for dims >= 1
   DevBuf vtd;                 // T [nt] v~_j
+  int step3 = 0;              // 0: radial precomputed A, 1: direct t-sum
+  int64_t a_rows = 0;         // distinct |n|^2 values (rows of A)
+  int nkp = 0;                // table width: nk rounded up to even
+  DevBuf atab;                // T [a_rows][nkp(nkp+1)/2] upper triangle of A_k'k(|n|^2)
+  DevBuf rowidx;              // int32 [d M^2 + 1]: |n|^2 -> row (d >= 2)
   DevBuf dec;                 // T [d][M+1] 1/psi^(2 pi n / nf_r)
   DevBuf tw[3];               // FFT twiddles per distinct length (T complex)
   DevBuf tw4;                 // four-step twiddles (1-D, T complex, length nf)

@@ -27,6 +27,14 @@ namespace gp {
 void build_records_into(Plan* P, int64_t n, const double* pts, const double* sig,
                         const double* l, DevBuf& perm, DevBuf& cell, DevBuf& frac, DevBuf& spn,
                         DevBuf& pref, DevBuf& bin_start, int* out_of_box);
+void mix_modes_fp64(Plan* P);
+void mix_modes_fp32(Plan* P);
+static void mix_modes(Plan* P) {
+  if (P->precision == GP_FP64)
+    mix_modes_fp64(P);
+  else
+    mix_modes_fp32(P);
+}
 
 namespace {
 
@@ -325,115 +333,6 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(
   }
 }
 
-// ------------------------------------------------------------------ mode ----
-struct ModeArgs {
-  int d;
-  int64_t M, mc, F;       // mc = 2M+1, F = mc^d
-  int nk, npair, nt;
-  int64_t pair_stride;
-  int fourstep;
-  int64_t nf, L1, L2;
-};
-
-__device__ __forceinline__ int64_t mode_store(const ModeArgs& a, int64_t f, const int64_t* nv) {
-  if (!a.fourstep) return f;
-  int64_t k = nv[0] % a.nf;
-  if (k < 0) k += a.nf;
-  return (k % a.L2) * a.L1 + (k / a.L2);
-}
-
-// Each thread owns a mode pair (n, -n) of every complex grid: it unpacks the two
-// real spectra b_2g, b_2g+1, deconvolves, applies
-//   a_k'[n] = sum_j v~_j G^_k'j[n] sum_k G^_kj[n] b_k[n]     (step 3, rem:step3 direct)
-// re-deconvolves and packs the result back in place.
-template <typename T, int NK>
-__global__ __launch_bounds__(kThreads) void mode_kernel(
-    ModeArgs a, typename V2<T>::type* __restrict__ C, const T* __restrict__ gtab,
-    const T* __restrict__ etab, const T* __restrict__ vt, const T* __restrict__ dec) {
-  using V = typename V2<T>::type;
-  const int64_t f = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  const int64_t half = (a.F + 1) / 2;
-  if (f >= half) return;
-  const int64_t fc = a.F - 1 - f;
-  int64_t nv[3] = {0, 0, 0}, nvc[3] = {0, 0, 0};
-  int64_t an[3] = {0, 0, 0};
-  {
-    int64_t q = f;
-    for (int r = 0; r < a.d; ++r) {
-      nv[r] = q % a.mc - a.M;
-      q /= a.mc;
-      nvc[r] = -nv[r];
-      an[r] = nv[r] < 0 ? -nv[r] : nv[r];
-    }
-  }
-  const int64_t M1 = a.M + 1;
-  T D = T(1);
-  for (int r = 0; r < a.d; ++r) D *= dec[r * M1 + an[r]];
-  const int64_t s0 = mode_store(a, f, nv), s1 = mode_store(a, fc, nvc);
-  V b[NK], acc[NK];
-#pragma unroll
-  for (int g = 0; g < NK / 2; ++g) {
-    V z = V{T(0), T(0)}, zc = V{T(0), T(0)};
-    if (g < a.npair) {
-      z = C[g * a.pair_stride + s0];
-      zc = C[g * a.pair_stride + s1];
-    }
-    b[2 * g] = V{T(0.5) * (z.x + zc.x) * D, T(0.5) * (z.y - zc.y) * D};
-    b[2 * g + 1] = V{T(0.5) * (z.y + zc.y) * D, T(-0.5) * (z.x - zc.x) * D};
-    acc[2 * g] = V{T(0), T(0)};
-    acc[2 * g + 1] = V{T(0), T(0)};
-  }
-  const int nk = a.nk;
-  for (int j = 0; j < a.nt; ++j) {
-    const T* g0 = gtab + ((int64_t)j * nk) * M1 + an[0];
-    const T* e1 = etab + ((int64_t)j * nk) * M1 + an[1];
-    const T* e2 = etab + ((int64_t)j * nk) * M1 + an[2];
-    T gk[NK];
-    V s = V{T(0), T(0)};
-#pragma unroll
-    for (int k = 0; k < NK; ++k) {
-      T g = T(0);
-      if (k < nk) {
-        g = g0[k * M1];
-        if (a.d > 1) g *= e1[k * M1];
-        if (a.d > 2) g *= e2[k * M1];
-      }
-      gk[k] = g;
-      s.x += g * b[k].x;
-      s.y += g * b[k].y;
-    }
-    const T v = vt[j];
-    s.x *= v;
-    s.y *= v;
-#pragma unroll
-    for (int k = 0; k < NK; ++k) {
-      acc[k].x += gk[k] * s.x;
-      acc[k].y += gk[k] * s.y;
-    }
-  }
-#pragma unroll
-  for (int g = 0; g < NK / 2; ++g) {
-    if (g >= a.npair) break;
-    const V p = V{acc[2 * g].x * D, acc[2 * g].y * D};
-    const V q = V{acc[2 * g + 1].x * D, acc[2 * g + 1].y * D};
-    C[g * a.pair_stride + s0] = V{p.x - q.y, p.y + q.x};
-    if (s1 != s0) C[g * a.pair_stride + s1] = V{p.x + q.y, -p.y + q.x};
-  }
-}
-
-// 1-D four-step: zero the spectrum outside {-M..M} before the inverse transform.
-template <typename T>
-__global__ void zero_band_kernel(typename V2<T>::type* C, int64_t nf, int64_t L1, int64_t L2,
-                                 int64_t M, int npair) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nf * npair) return;
-  const int64_t idx = e % nf;
-  const int64_t k2 = idx / L1, k1 = idx % L1;
-  const int64_t k = k2 + L2 * k1;
-  const int64_t n = k <= nf / 2 ? k : k - nf;
-  if (n > M || n < -M) C[e] = typename V2<T>::type{T(0), T(0)};
-}
-
 __global__ void gather_kernel(int64_t n, const int* __restrict__ perm, const double* __restrict__ u,
                               double* __restrict__ s) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -561,44 +460,6 @@ void interp_dispatch(Plan* P, int64_t n, const DevBuf& cell, const DevBuf& frac,
 #undef GP_I
 }
 
-template <typename T, int NK>
-void launch_mode_nk(Plan* P) {
-  PhaseScope ps(P, PH_MODE);
-  ModeArgs a;
-  a.d = P->d;
-  a.M = P->M;
-  a.mc = P->mcount;
-  a.F = 1;
-  for (int r = 0; r < P->d; ++r) a.F *= a.mc;
-  a.nk = P->nk;
-  a.npair = P->npair;
-  a.nt = P->nt_eff;
-  a.fourstep = P->fourstep;
-  a.nf = P->nf[0];
-  a.L1 = P->L1;
-  a.L2 = P->L2;
-  a.pair_stride = P->fourstep ? P->nf[0] : a.F;
-  const int64_t half = (a.F + 1) / 2;
-  hipLaunchKernelGGL((mode_kernel<T, NK>), dim3((unsigned)((half + kThreads - 1) / kThreads)),
-                     dim3(kThreads), 0, P->stream, a, P->gridC.as<typename V2<T>::type>(),
-                     P->gtab.as<T>(), P->etab.as<T>(), P->vtd.as<T>(), P->dec.as<T>());
-  GP_CHECK_LAUNCH();
-}
-
-template <typename T>
-void launch_mode(Plan* P) {
-  const int nk2 = 2 * P->npair;
-  switch (nk2) {
-#define GP_M(N) case N: launch_mode_nk<T, N>(P); break;
-    GP_M(2) GP_M(4) GP_M(6) GP_M(8) GP_M(10) GP_M(12) GP_M(14) GP_M(16) GP_M(18) GP_M(20)
-    GP_M(22) GP_M(24) GP_M(26) GP_M(28) GP_M(30) GP_M(32) GP_M(34) GP_M(36) GP_M(38) GP_M(40)
-    GP_M(42) GP_M(44) GP_M(46) GP_M(48)
-#undef GP_M
-    default:
-      throw Error{GP_EUNSUPPORTED, "too many Chebyshev nodes"};
-  }
-}
-
 // Forward (sign -1) FFT of every grid pair: active box -> truncated modes.
 // Inverse (sign +1): truncated modes -> active box.
 void fft_all(Plan* P, int sign) {
@@ -699,14 +560,7 @@ template <typename T>
 void forward_and_mix(Plan* P, const double* xs) {
   spread_dispatch<T>(P, xs);
   fft_all(P, -1);
-  launch_mode<T>(P);
-  if (P->fourstep) {
-    const int64_t tot = (int64_t)P->nf[0] * P->npair;
-    hipLaunchKernelGGL(zero_band_kernel<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
-                       P->stream, P->gridC.as<typename V2<T>::type>(), (int64_t)P->nf[0],
-                       (int64_t)P->L1, (int64_t)P->L2, P->M, P->npair);
-    GP_CHECK_LAUNCH();
-  }
+  mix_modes(P);
   fft_all(P, +1);
 }
 

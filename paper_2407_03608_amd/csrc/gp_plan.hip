@@ -239,6 +239,34 @@ __global__ void scatter_records_kernel(int d, int64_t n, const int* __restrict__
   pref[pos] = pf_tmp[i];
 }
 
+// Row r of the precomputed step-3 tensor (rem:step3) at |n|^2 = svals[r]:
+//   A_k'k = sum_j v~_j G^_k'j G^_kj = sum_j v~_j C_k'j C_kj exp(-(tau_k'j + tau_kj) |n|^2)
+// (eq:Gkt on the grid), one thread per (row, upper-triangle entry), fp64.
+template <typename T>
+__global__ void atab_kernel(int64_t rows, int npk, int nkp, int nk, int nt,
+                            const double* __restrict__ svals, const double* __restrict__ tau,
+                            const double* __restrict__ cst, const double* __restrict__ vt,
+                            T* __restrict__ A) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * npk) return;
+  const int64_t r = e / npk;
+  int p = (int)(e - r * npk);
+  int k1 = 0;
+  while (p >= nkp - k1) {
+    p -= nkp - k1;
+    ++k1;
+  }
+  const int k2 = k1 + p;
+  double sum = 0;
+  if (k1 < nk && k2 < nk) {
+    const double sv = svals[r];
+    for (int j = 0; j < nt; ++j)
+      sum += vt[j] * cst[j * nk + k1] * cst[j * nk + k2] *
+             exp(-(tau[j * nk + k1] + tau[j * nk + k2]) * sv);
+  }
+  A[e] = (T)sum;
+}
+
 }  // namespace
 
 // Sort a point set into the plan's tiles and build its records (used for the
@@ -552,6 +580,37 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
   P->nk = P->n_sigma + 1;
   P->npair = (P->nk + 1) / 2;
 
+  // ---- step 3 variant; radial rows of the precomputed tensor
+  P->step3 = opts.step3 ? 1 : 0;
+  P->nkp = P->nk + (P->nk & 1);
+  std::vector<double> svals;
+  std::vector<int> rowmap;
+  if (P->step3 == 0) {
+    const int64_t M = P->M;
+    if (d == 1) {
+      svals.resize(M + 1);
+      for (int64_t m = 0; m <= M; ++m) svals[m] = (double)(m * m);
+    } else {
+      const int64_t smax = (int64_t)d * M * M;
+      std::vector<char> present(smax + 1, 0);
+      if (d == 2) {
+        for (int64_t a0 = 0; a0 <= M; ++a0)
+          for (int64_t a1 = 0; a1 <= M; ++a1) present[a0 * a0 + a1 * a1] = 1;
+      } else {
+        for (int64_t a0 = 0; a0 <= M; ++a0)
+          for (int64_t a1 = 0; a1 <= M; ++a1)
+            for (int64_t a2 = 0; a2 <= M; ++a2) present[a0 * a0 + a1 * a1 + a2 * a2] = 1;
+      }
+      rowmap.assign(smax + 1, -1);
+      for (int64_t v = 0; v <= smax; ++v)
+        if (present[v]) {
+          rowmap[v] = (int)svals.size();
+          svals.push_back((double)v);
+        }
+    }
+    P->a_rows = (int64_t)svals.size();
+  }
+
   // ---- memory
   const size_t cs = P->precision == GP_FP64 ? 16 : 8;  // complex element
   const size_t ts = cs / 2;
@@ -576,7 +635,10 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
   bytes += (size_t)G * (szA + szB + szB2 + szC) * cs;
   bytes += (size_t)n * (sizeof(int) * (1 + d) + ts * d + 2 * sizeof(double));
   bytes += (size_t)(P->n_bins + 1) * sizeof(int);
-  bytes += (size_t)P->nt_eff * P->nk * (P->M + 1) * ts * 2;
+  if (P->step3 == 0)
+    bytes += (size_t)P->a_rows * (P->nkp * (P->nkp + 1) / 2) * ts + rowmap.size() * sizeof(int);
+  else
+    bytes += (size_t)P->nt_eff * P->nk * (P->M + 1) * ts * 2;
   bytes += (size_t)n * 8 * sizeof(double);  // vectors
   bytes += (size_t)nf * cs * 2;
   P->device_bytes = bytes;
@@ -651,8 +713,47 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
       GP_HIP(hipStreamSynchronize(s));
     }
   };
-  upload(P->gtab, g0);
-  upload(P->etab, e1);
+  if (P->step3 == 1) {
+    upload(P->gtab, g0);
+    upload(P->etab, e1);
+  } else {
+    // precomputed tensor, one row per distinct |n|^2
+    std::vector<double> tau((size_t)P->nt_eff * P->nk), cst((size_t)P->nt_eff * P->nk);
+    for (int j = 0; j < P->nt_eff; ++j)
+      for (int k = 0; k < P->nk; ++k) {
+        double s2 = P->sig_nodes[k] * P->sig_nodes[k] * P->chi[j] * P->chi[j];
+        cst[j * P->nk + k] = std::pow(2 * PI * s2, 0.5 * d);
+        tau[j * P->nk + k] = 2 * PI * PI * s2 * P->dw * P->dw;
+      }
+    DevBuf dsv, dtau, dcst, dvt;
+    auto up64 = [&](DevBuf& b, const std::vector<double>& v) {
+      b.alloc(v.size() * sizeof(double));
+      GP_HIP(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    };
+    up64(dsv, svals);
+    up64(dtau, tau);
+    up64(dcst, cst);
+    up64(dvt, P->vt);
+    const int npk = P->nkp * (P->nkp + 1) / 2;
+    const int64_t tot = P->a_rows * npk;
+    P->atab.alloc((size_t)tot * ts);
+    const unsigned nb = (unsigned)((tot + 255) / 256);
+    if (P->precision == GP_FP64)
+      hipLaunchKernelGGL(atab_kernel<double>, dim3(nb), dim3(256), 0, s, P->a_rows, npk, P->nkp,
+                         P->nk, P->nt_eff, dsv.as<double>(), dtau.as<double>(), dcst.as<double>(),
+                         dvt.as<double>(), P->atab.as<double>());
+    else
+      hipLaunchKernelGGL(atab_kernel<float>, dim3(nb), dim3(256), 0, s, P->a_rows, npk, P->nkp,
+                         P->nk, P->nt_eff, dsv.as<double>(), dtau.as<double>(), dcst.as<double>(),
+                         dvt.as<double>(), P->atab.as<float>());
+    GP_CHECK_LAUNCH();
+    if (d > 1) {
+      P->rowidx.alloc(rowmap.size() * sizeof(int));
+      GP_HIP(hipMemcpyAsync(P->rowidx.p, rowmap.data(), rowmap.size() * sizeof(int),
+                            hipMemcpyHostToDevice, s));
+    }
+    GP_HIP(hipStreamSynchronize(s));
+  }
   upload(P->vtd, P->vt);
   upload(P->dec, dec);
   P->nodes_d.alloc(P->nk * sizeof(double));

@@ -62,6 +62,20 @@ def test_matvec_fp64_vs_oracle(gp, d, n, M, nu):
     _check_matvec(gp, prob, tol=1e-9, M=M)
 
 
+@pytest.mark.parametrize("d,M,prec", [(1, 150, 0), (2, 24, 0), (3, 8, 0), (2, 24, 1), (1, 2600, 0)])
+def test_step3_variants_agree(gp, d, M, prec):
+    """rem:step3: the precomputed tensor (one row per |n|^2) and the direct t-sum
+    give the same operator, and both match the oracle."""
+    lmin, lmax = (0.01, 0.03) if M > 1000 else (0.08, 0.2)
+    prob = inputs.random_small(d, 300, seed=50 + d, nu=1.5, lmin=lmin, lmax=lmax)
+    tol = 1e-9 if prec == 0 else 1e-4
+    bar = FP64_TOL if prec == 0 else FP32_TOL
+    Pr, info_r, a, got_r, ref = _check_matvec(gp, prob, tol=tol, precision=prec, bar=bar, M=M, step3=0)
+    Pd, info_d, _, got_d, _ = _check_matvec(gp, prob, tol=tol, precision=prec, bar=bar, M=M, step3=1)
+    assert info_r["step3"] == 0 and info_d["step3"] == 1 and info_r["a_rows"] > 0
+    assert rel(got_r, got_d) < (1e-11 if prec == 0 else 1e-5)
+
+
 @pytest.mark.parametrize("d,n,M", [(1, 300, 150), (2, 600, 24), (3, 300, 8)])
 def test_matvec_fp32_vs_oracle(gp, d, n, M):
     prob = inputs.random_small(d, n, seed=3 + d, nu=1.5, lmin=0.08, lmax=0.2)
