@@ -153,7 +153,16 @@ __global__ __launch_bounds__(B*(L / EPT)) void fft_pass_kernel(
   constexpr int TPT = L / EPT;
   constexpr int NTHR = B * TPT;
   __shared__ V buf[B * L];
-  const int64_t t0 = (int64_t)blockIdx.x * B;
+  // Workgroups go to the 8 XCDs round-robin by id.  For strided (column)
+  // passes, give each XCD a contiguous range of transforms so neighbouring
+  // columns, which share cache lines, run on the same XCD (same L2).
+  int64_t bid = blockIdx.x;
+  if (p.inner > 1) {
+    const int64_t nb = gridDim.x, q = nb / 8, r = nb % 8;
+    const int64_t x = bid % 8, slot = bid / 8;
+    bid = x < r ? x * (q + 1) + slot : r * (q + 1) + (x - r) * q + slot;
+  }
+  const int64_t t0 = bid * B;
 
   for (int e = threadIdx.x; e < B * L; e += NTHR) {
     int b, pos;

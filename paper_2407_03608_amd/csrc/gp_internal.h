@@ -66,6 +66,19 @@ struct FftPass {
 void fft_pass(int fp64, const FftPass& p, const void* in, void* out, const void* twiddles,
               hipStream_t s);
 
+// ---------------------------------------------------------- point records --
+// A point set sorted into the spreading tiles.  Each point carries its first
+// window cell per dimension and a row of `rs` T values: the d*w window values
+// psi(cell + q - g) followed by the nkp weights w_k(x) of eq:Wk.
+struct Records {
+  int64_t n = 0;
+  int rs = 0;                 // row length of pw (T elements)
+  DevBuf perm;                // int32  [n] sorted -> caller index
+  DevBuf cell;                // int32  [d][n] first window cell in the active box
+  DevBuf pw;                  // T      [n][rs] window values and w_k
+  DevBuf bin_start;           // int32  [n_bins + 1]
+};
+
 // ------------------------------------------------------------------- plan --
 struct Plan {
   // problem
@@ -107,12 +120,7 @@ struct Plan {
   std::vector<double> sig_nodes, bary, vt, chi;
   // device data
   hipStream_t stream = nullptr;
-  DevBuf perm;                // int32  sorted -> caller index
-  DevBuf cell;                // int32  [d][n] start cell in the active box
-  DevBuf frac;                // T      [d][n] offset of the first cell from the point
-  DevBuf spn;                 // double [n] sigma_p of the point (mapped)
-  DevBuf pref;                // double [n] s(x) (2/(pi l'^2))^(d/4)
-  DevBuf bin_start;           // int32  [n_bins + 1]
+  Records rec;                // the training points, bin-sorted
   DevBuf nodes_d;             // double [nk] sigma_k
   DevBuf bary_d;              // double [nk] barycentric weights
   DevBuf gtab;                // T [nt][nk][M+1]: C_kj * exp(-tau_kj n^2) for dim 0

@@ -25,8 +25,7 @@
 namespace gp {
 
 void build_records_into(Plan* P, int64_t n, const double* pts, const double* sig,
-                        const double* l, DevBuf& perm, DevBuf& cell, DevBuf& frac, DevBuf& spn,
-                        DevBuf& pref, DevBuf& bin_start, int* out_of_box);
+                        const double* l, Records& R, int* out_of_box);
 void mix_modes_fp64(Plan* P);
 void mix_modes_fp32(Plan* P);
 static void mix_modes(Plan* P) {
@@ -59,50 +58,30 @@ struct NuArgs {
   int add_noise, first_chunk;
 };
 
-template <typename T> __device__ __forceinline__ T es_kernel(T z, T two_over_w, T beta) {
-  T a = z * two_over_w;
-  T q = T(1) - a * a;
-  return q >= T(0) ? exp(beta * (sqrt(q) - T(1))) : T(0);
-}
-
-// Lagrange basis on the Chebyshev-Lobatto nodes (eq:chebscheme) in barycentric
-// form: P_k(s) = (lam_k/(s - s_k)) / sum_j lam_j/(s - s_j); P_k = delta at a node.
-__device__ __forceinline__ double bary_den(double s, const double* __restrict__ nodes,
-                                           const double* __restrict__ bary, int nk, int* hit) {
-  double den = 0;
-  *hit = -1;
-  for (int k = 0; k < nk; ++k) {
-    double dk = s - nodes[k];
-    if (dk == 0.0) {
-      *hit = k;
-      return 1.0;
-    }
-    den += bary[k] / dk;
-  }
-  return den;
-}
-__device__ __forceinline__ double bary_p(int k, double s, double den, int hit,
-                                         const double* __restrict__ nodes,
-                                         const double* __restrict__ bary) {
-  if (hit >= 0) return k == hit ? 1.0 : 0.0;
-  return bary[k] / (s - nodes[k]) / den;
-}
+// Points are staged in LDS in batches of kPB: the first window cell per
+// dimension, the point's row of window values and weights (padded to an odd
+// stride so that lanes reading different points hit different banks) and x_i.
+__host__ __device__ constexpr int lds_stride(int rs) { return rs | 1; }
 
 // ---------------------------------------------------------------- spread ----
-template <typename T, int D, int WT>
+// One workgroup per tile of the active grid and chunk of complex grids.  The
+// sources are the bins whose points' windows can reach the tile (nsrc per
+// dimension).  Work items are (point, window row, grid pair); each adds its
+// row of w cells into the LDS tile with LDS atomics.
+template <typename T, int D>
 __global__ __launch_bounds__(kThreads) void spread_kernel(
     NuArgs a, const double* __restrict__ x, const int* __restrict__ cell,
-    const T* __restrict__ frac, const double* __restrict__ spn, const double* __restrict__ pref,
-    const int* __restrict__ bin_start, const double* __restrict__ nodes,
-    const double* __restrict__ bary, typename V2<T>::type* __restrict__ grid) {
+    const T* __restrict__ pw, int rs, const int* __restrict__ bin_start,
+    typename V2<T>::type* __restrict__ grid) {
   using V = typename V2<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   const int tc0 = a.tile[0], tc1 = D > 1 ? a.tile[1] : 1, tc2 = D > 2 ? a.tile[2] : 1;
   const int tcells = tc0 * tc1 * tc2;
+  const int ls = lds_stride(rs);
   V* acc = reinterpret_cast<V*>(smem);
-  T* s_psi = reinterpret_cast<T*>(acc + (size_t)a.gc * tcells);  // [kPB][D][WT]
-  T* s_c = s_psi + kPB * D * WT;                                  // [kPB][2*kGC]
-  int* s_cell = reinterpret_cast<int*>(s_c + kPB * 2 * kGC);      // [kPB][D]
+  T* s_rec = reinterpret_cast<T*>(acc + (size_t)a.gc * tcells);  // [kPB][ls]
+  T* s_x = s_rec + kPB * ls;                                      // [kPB]
+  int* s_cell = reinterpret_cast<int*>(s_x + kPB);                // [kPB][D]
 
   int tcoord[3] = {0, 0, 0}, t0[3] = {0, 0, 0};
   {
@@ -114,14 +93,13 @@ __global__ __launch_bounds__(kThreads) void spread_kernel(
     }
   }
   for (int e = threadIdx.x; e < a.gc * tcells; e += kThreads) acc[e] = V{T(0), T(0)};
-  __syncthreads();
 
-  const T two_over_w = T(2) / T(a.w);
-  const T beta = (T)a.beta;
+  const int w = a.w;
+  const int wko = D * w + 2 * a.g0;  // offset of w_{2 g0} in a row
   int nsrc_tot = 1;
   for (int r = 0; r < D; ++r) nsrc_tot *= a.nsrc;
   int rows = 1;
-  for (int r = 1; r < D; ++r) rows *= a.w;
+  for (int r = 1; r < D; ++r) rows *= w;
 
   for (int sb = 0; sb < nsrc_tot; ++sb) {
     int64_t bin = 0, mul = 1;
@@ -138,26 +116,14 @@ __global__ __launch_bounds__(kThreads) void spread_kernel(
     const int p0 = bin_start[bin], p1 = bin_start[bin + 1];
     for (int pb = p0; pb < p1; pb += kPB) {
       const int np = min(kPB, p1 - pb);
+      __syncthreads();  // previous batch (or the tile clear) done
+      for (int e = threadIdx.x; e < np * rs; e += kThreads) {
+        const int p = e / rs;
+        s_rec[p * ls + (e - p * rs)] = pw[(int64_t)pb * rs + e];
+      }
       if (threadIdx.x < np) {
-        const int64_t i = pb + threadIdx.x;
-        for (int r = 0; r < D; ++r) {
-          s_cell[threadIdx.x * D + r] = cell[r * a.n + i];
-          T del = frac[r * a.n + i];
-#pragma unroll
-          for (int qq = 0; qq < WT; ++qq)
-            s_psi[(threadIdx.x * D + r) * WT + qq] =
-                qq < a.w ? es_kernel<T>(del + T(qq), two_over_w, beta) : T(0);
-        }
-        const double sp = spn[i];
-        int hit;
-        const double den = bary_den(sp, nodes, bary, a.nk, &hit);
-        const double sc = pref[i] * x[i];
-        for (int kk = 0; kk < 2 * kGC; ++kk) {
-          const int k = 2 * a.g0 + kk;
-          double v = 0;
-          if (kk < 2 * a.gc && k < a.nk) v = sc * bary_p(k, sp, den, hit, nodes, bary);
-          s_c[threadIdx.x * 2 * kGC + kk] = (T)v;
-        }
+        s_x[threadIdx.x] = (T)x[pb + threadIdx.x];
+        for (int r = 0; r < D; ++r) s_cell[threadIdx.x * D + r] = cell[r * a.n + pb + threadIdx.x];
       }
       __syncthreads();
       const int nitems = np * rows * a.gc;
@@ -166,36 +132,37 @@ __global__ __launch_bounds__(kThreads) void spread_kernel(
         const int rest = it / np;
         const int row = rest % rows;
         const int g = rest / rows;
-        // outer (dims >= 1) cell offsets of this row
-        int loc[3] = {0, 0, 0};
+        const T* pr = s_rec + p * ls;
+        int loc1 = 0, loc2 = 0;
         T wv = T(1);
         bool inside = true;
-        int rr = row;
-        for (int r = 1; r < D; ++r) {
-          const int qr = rr % a.w;
-          rr /= a.w;
-          const int cr = s_cell[p * D + r] + qr - t0[r];
-          if (cr < 0 || cr >= a.tile[r]) inside = false;
-          loc[r] = cr;
-          wv *= s_psi[(p * D + r) * WT + qr];
+        if (D > 1) {
+          const int q1 = row % w;
+          loc1 = s_cell[p * D + 1] + q1 - t0[1];
+          inside = inside && loc1 >= 0 && loc1 < tc1;
+          wv *= pr[w + q1];
+        }
+        if (D > 2) {
+          const int q2 = row / w;
+          loc2 = s_cell[p * D + 2] + q2 - t0[2];
+          inside = inside && loc2 >= 0 && loc2 < tc2;
+          wv *= pr[2 * w + q2];
         }
         if (!inside) continue;
-        const T c0 = s_c[p * 2 * kGC + 2 * g], c1 = s_c[p * 2 * kGC + 2 * g + 1];
+        const T xa = s_x[p];
+        const T c0 = pr[wko + 2 * g] * xa * wv, c1 = pr[wko + 2 * g + 1] * xa * wv;
         const int base0 = s_cell[p * D] - t0[0];
-        V* accg = acc + (size_t)g * tcells + (loc[2] * tc1 + loc[1]) * tc0;
-#pragma unroll
-        for (int q0 = 0; q0 < WT; ++q0) {
-          const int c = base0 + q0;
-          if (q0 < a.w && c >= 0 && c < tc0) {
-            const T v = wv * s_psi[(p * D) * WT + q0];
-            atomicAdd(&accg[c].x, c0 * v);
-            atomicAdd(&accg[c].y, c1 * v);
-          }
+        V* accg = acc + (size_t)g * tcells + (loc2 * tc1 + loc1) * tc0;
+        const int qa = max(0, -base0), qb = min(w, tc0 - base0);
+        for (int q0 = qa; q0 < qb; ++q0) {
+          const T v = pr[q0];
+          atomicAdd(&accg[base0 + q0].x, c0 * v);
+          atomicAdd(&accg[base0 + q0].y, c1 * v);
         }
       }
-      __syncthreads();
     }
   }
+  __syncthreads();
   // write the tile (exclusively owned: plain stores)
   for (int e = threadIdx.x; e < a.gc * tcells; e += kThreads) {
     const int g = e / tcells;
@@ -211,26 +178,26 @@ __global__ __launch_bounds__(kThreads) void spread_kernel(
 }
 
 // ---------------------------------------------------------------- interp ----
-// One workgroup per bin.  For each chunk of complex grids, the bin's tile plus
+// One workgroup per bin.  For each chunk of complex grids the bin's tile plus
 // its (w-1) halo is staged in LDS; every (point, grid pair) item sums its
-// window and adds w_2g beta_2g + w_2g+1 beta_2g+1 into the point's accumulator.
-template <typename T, int D, int WT>
+// window and adds w_2g beta_2g + w_2g+1 beta_2g+1 to the point's accumulator.
+template <typename T, int D>
 __global__ __launch_bounds__(kThreads) void interp_kernel(
     NuArgs a, const typename V2<T>::type* __restrict__ grid, const int* __restrict__ cell,
-    const T* __restrict__ frac, const double* __restrict__ spn, const double* __restrict__ pref,
-    const int* __restrict__ bin_start, const double* __restrict__ nodes,
-    const double* __restrict__ bary, const double* __restrict__ x, double* __restrict__ y) {
+    const T* __restrict__ pw, int rs, const int* __restrict__ bin_start,
+    const double* __restrict__ x, double* __restrict__ y) {
   using V = typename V2<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
-  const int pc0 = a.tile[0] + a.w - 1;
-  const int pc1 = D > 1 ? a.tile[1] + a.w - 1 : 1;
-  const int pc2 = D > 2 ? a.tile[2] + a.w - 1 : 1;
+  const int w = a.w;
+  const int pc0 = a.tile[0] + w - 1;
+  const int pc1 = D > 1 ? a.tile[1] + w - 1 : 1;
+  const int pc2 = D > 2 ? a.tile[2] + w - 1 : 1;
   const int pcells = pc0 * pc1 * pc2;
-  V* tileA = reinterpret_cast<V*>(smem);                               // [gc][pcells]
-  T* s_psi = reinterpret_cast<T*>(tileA + (size_t)a.gc * pcells);      // [kPB][D][WT]
-  T* s_wk = s_psi + kPB * D * WT;                                      // [kPB][2*kGC]
-  double* s_acc = reinterpret_cast<double*>(s_wk + kPB * 2 * kGC);    // [kPB]
-  int* s_cell = reinterpret_cast<int*>(s_acc + kPB);                   // [kPB][D]
+  const int ls = lds_stride(rs);
+  V* tileA = reinterpret_cast<V*>(smem);                                  // [gc][pcells]
+  T* s_rec = reinterpret_cast<T*>(tileA + (size_t)a.gc * pcells);         // [kPB][ls]
+  double* s_acc = reinterpret_cast<double*>(s_rec + kPB * ls);            // [kPB] (8-B aligned: kPB*ls*sizeof(T) is a multiple of 256)
+  int* s_cell = reinterpret_cast<int*>(s_acc + kPB);                      // [kPB][D]
 
   const int64_t bin = blockIdx.x;
   const int p0 = bin_start[bin], p1 = bin_start[bin + 1];
@@ -243,7 +210,6 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(
       tb /= a.nbins[r];
     }
   }
-  // stage the padded tile of the chunk's grids
   for (int e = threadIdx.x; e < a.gc * pcells; e += kThreads) {
     const int g = e / pcells;
     int c = e - g * pcells;
@@ -258,33 +224,18 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(
                (int64_t)c1 * a.gstride[1] + (int64_t)c2 * a.gstride[2]];
     tileA[e] = v;
   }
-  __syncthreads();
-
-  const T two_over_w = T(2) / T(a.w);
-  const T beta = (T)a.beta;
+  const int wko = D * w + 2 * a.g0;
   int cellsw = 1;
-  for (int r = 1; r < D; ++r) cellsw *= a.w;
+  for (int r = 1; r < D; ++r) cellsw *= w;
   for (int pb = p0; pb < p1; pb += kPB) {
     const int np = min(kPB, p1 - pb);
+    __syncthreads();
+    for (int e = threadIdx.x; e < np * rs; e += kThreads) {
+      const int p = e / rs;
+      s_rec[p * ls + (e - p * rs)] = pw[(int64_t)pb * rs + e];
+    }
     if (threadIdx.x < np) {
-      const int64_t i = pb + threadIdx.x;
-      for (int r = 0; r < D; ++r) {
-        s_cell[threadIdx.x * D + r] = cell[r * a.n + i] - t0[r];
-        T del = frac[r * a.n + i];
-#pragma unroll
-        for (int qq = 0; qq < WT; ++qq)
-          s_psi[(threadIdx.x * D + r) * WT + qq] =
-              qq < a.w ? es_kernel<T>(del + T(qq), two_over_w, beta) : T(0);
-      }
-      const double sp = spn[i];
-      int hit;
-      const double den = bary_den(sp, nodes, bary, a.nk, &hit);
-      for (int kk = 0; kk < 2 * kGC; ++kk) {
-        const int k = 2 * a.g0 + kk;
-        double v = 0;
-        if (kk < 2 * a.gc && k < a.nk) v = pref[i] * bary_p(k, sp, den, hit, nodes, bary);
-        s_wk[threadIdx.x * 2 * kGC + kk] = (T)v;
-      }
+      for (int r = 0; r < D; ++r) s_cell[threadIdx.x * D + r] = cell[r * a.n + pb + threadIdx.x] - t0[r];
       s_acc[threadIdx.x] = 0.0;
     }
     __syncthreads();
@@ -292,44 +243,42 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(
     for (int it = threadIdx.x; it < nitems; it += kThreads) {
       const int p = it % np;
       const int g = it / np;
-      const V* tg = tileA + (size_t)g * pcells;
+      const T* pr = s_rec + p * ls;
+      const V* tg = tileA + (size_t)g * pcells + s_cell[p * D];
       T sx = 0, sy = 0;
       for (int row = 0; row < cellsw; ++row) {
-        int rr = row;
         T wv = T(1);
-        int off = 0, mulo = pc0;
-        for (int r = 1; r < D; ++r) {
-          const int qr = rr % a.w;
-          rr /= a.w;
-          wv *= s_psi[(p * D + r) * WT + qr];
-          off += (s_cell[p * D + r] + qr) * mulo;
-          mulo *= (r == 1 ? pc1 : pc2);
+        int off = 0;
+        if (D > 1) {
+          const int q1 = row % w;
+          wv *= pr[w + q1];
+          off += (s_cell[p * D + 1] + q1) * pc0;
         }
-        const V* tr = tg + off + s_cell[p * D];
+        if (D > 2) {
+          const int q2 = row / w;
+          wv *= pr[2 * w + q2];
+          off += (s_cell[p * D + 2] + q2) * pc0 * pc1;
+        }
+        const V* tr = tg + off;
         T rx = 0, ry = 0;
-#pragma unroll
-        for (int q0 = 0; q0 < WT; ++q0) {
-          if (q0 < a.w) {
-            const T ps = s_psi[(p * D) * WT + q0];
-            const V gv = tr[q0];
-            rx += ps * gv.x;
-            ry += ps * gv.y;
-          }
+        for (int q0 = 0; q0 < w; ++q0) {
+          const T ps = pr[q0];
+          const V gv = tr[q0];
+          rx += ps * gv.x;
+          ry += ps * gv.y;
         }
         sx += wv * rx;
         sy += wv * ry;
       }
-      const double contrib = (double)s_wk[p * 2 * kGC + 2 * g] * (double)sx +
-                             (double)s_wk[p * 2 * kGC + 2 * g + 1] * (double)sy;
+      const double contrib = (double)pr[wko + 2 * g] * (double)sx + (double)pr[wko + 2 * g + 1] * (double)sy;
       atomicAdd(&s_acc[p], contrib);
     }
     __syncthreads();
     if (threadIdx.x < np) {
       const int64_t i = pb + threadIdx.x;
-      double base = a.first_chunk ? (a.add_noise ? a.eta2 * x[i] : 0.0) : y[i];
+      const double base = a.first_chunk ? (a.add_noise ? a.eta2 * x[i] : 0.0) : y[i];
       y[i] = base + s_acc[threadIdx.x];
     }
-    __syncthreads();
   }
 }
 
@@ -345,20 +294,18 @@ __global__ void scatter_kernel(int64_t n, const int* __restrict__ perm, const do
 }
 
 // ------------------------------------------------------------- launchers ----
-int wt_for(int w) { return w <= 8 ? 8 : 16; }
-
 template <typename T>
-size_t spread_smem(const Plan* P, int gc, int WT) {
+size_t spread_smem(const Plan* P, int gc, int rs) {
   size_t tcells = (size_t)P->tile[0] * P->tile[1] * P->tile[2];
-  return gc * tcells * sizeof(typename V2<T>::type) + kPB * P->d * WT * sizeof(T) +
-         kPB * 2 * kGC * sizeof(T) + kPB * P->d * sizeof(int) + 16;
+  return gc * tcells * sizeof(typename V2<T>::type) + kPB * (lds_stride(rs) + 1) * sizeof(T) +
+         kPB * P->d * sizeof(int) + 16;
 }
 template <typename T>
-size_t interp_smem(const Plan* P, int gc, int WT) {
+size_t interp_smem(const Plan* P, int gc, int rs) {
   size_t pc = 1;
   for (int r = 0; r < P->d; ++r) pc *= (size_t)(P->tile[r] + P->w - 1);
-  return gc * pc * sizeof(typename V2<T>::type) + kPB * P->d * WT * sizeof(T) +
-         kPB * 2 * kGC * sizeof(T) + kPB * sizeof(double) + kPB * P->d * sizeof(int) + 16;
+  return gc * pc * sizeof(typename V2<T>::type) + (kPB * lds_stride(rs) + 1) * sizeof(T) +
+         kPB * sizeof(double) + kPB * P->d * sizeof(int) + 16;
 }
 
 constexpr size_t kSmemCap = 64 * 1024;
@@ -395,69 +342,60 @@ NuArgs nu_args(const Plan* P) {
   return a;
 }
 
-template <typename T, int D, int WT>
+template <typename T, int D>
 void launch_spread(Plan* P, const double* xs) {
   PhaseScope ps(P, PH_SPREAD);
   NuArgs a = nu_args(P);
+  const Records& R = P->rec;
   int gc = std::min(kGC, P->npair);
-  while (gc > 1 && spread_smem<T>(P, gc, WT) > kSmemCap) --gc;
+  while (gc > 1 && spread_smem<T>(P, gc, R.rs) > kSmemCap) --gc;
   const int nch = (P->npair + gc - 1) / gc;
   for (int ch = 0; ch < nch; ++ch) {
     a.g0 = ch * gc;
     a.gc = std::min(gc, P->npair - a.g0);
-    hipLaunchKernelGGL((spread_kernel<T, D, WT>), dim3((unsigned)P->n_bins), dim3(kThreads),
-                       spread_smem<T>(P, a.gc, WT), P->stream, a, xs, P->cell.as<int>(),
-                       P->frac.as<T>(), P->spn.as<double>(), P->pref.as<double>(),
-                       P->bin_start.as<int>(), P->nodes_d.as<double>(), P->bary_d.as<double>(),
+    hipLaunchKernelGGL((spread_kernel<T, D>), dim3((unsigned)P->n_bins), dim3(kThreads),
+                       spread_smem<T>(P, a.gc, R.rs), P->stream, a, xs, R.cell.as<int>(),
+                       R.pw.as<T>(), R.rs, R.bin_start.as<int>(),
                        P->gridA.as<typename V2<T>::type>());
     GP_CHECK_LAUNCH();
   }
 }
 
-template <typename T, int D, int WT>
-void launch_interp(Plan* P, int64_t n, const DevBuf& cell, const DevBuf& frac, const DevBuf& spn,
-                   const DevBuf& pref, const DevBuf& bin_start, const double* xs, double* ys,
-                   int add_noise) {
+template <typename T, int D>
+void launch_interp(Plan* P, const Records& R, const double* xs, double* ys, int add_noise) {
   PhaseScope ps(P, PH_INTERP);
   NuArgs a = nu_args(P);
-  a.n = n;
+  a.n = R.n;
   a.add_noise = add_noise;
   int gc = std::min(kGC, P->npair);
-  while (gc > 1 && interp_smem<T>(P, gc, WT) > kSmemCap) --gc;
+  while (gc > 1 && interp_smem<T>(P, gc, R.rs) > kSmemCap) --gc;
   const int nch = (P->npair + gc - 1) / gc;
+  // the 1-D four-step inverse leaves the grid in C (see fft_all)
+  const DevBuf& g = P->fourstep ? P->gridC : P->gridA;
   for (int ch = 0; ch < nch; ++ch) {
     a.g0 = ch * gc;
     a.gc = std::min(gc, P->npair - a.g0);
     a.first_chunk = ch == 0;
-    // the 1-D four-step inverse leaves the grid in C (see fft_all)
-    const DevBuf& g = P->fourstep ? P->gridC : P->gridA;
-    hipLaunchKernelGGL((interp_kernel<T, D, WT>), dim3((unsigned)P->n_bins), dim3(kThreads),
-                       interp_smem<T>(P, a.gc, WT), P->stream, a,
-                       g.as<typename V2<T>::type>(), cell.as<int>(), frac.as<T>(),
-                       spn.as<double>(), pref.as<double>(), bin_start.as<int>(),
-                       P->nodes_d.as<double>(), P->bary_d.as<double>(), xs, ys);
+    hipLaunchKernelGGL((interp_kernel<T, D>), dim3((unsigned)P->n_bins), dim3(kThreads),
+                       interp_smem<T>(P, a.gc, R.rs), P->stream, a,
+                       g.as<typename V2<T>::type>(), R.cell.as<int>(), R.pw.as<T>(), R.rs,
+                       R.bin_start.as<int>(), xs, ys);
     GP_CHECK_LAUNCH();
   }
 }
 
 template <typename T>
 void spread_dispatch(Plan* P, const double* xs) {
-  const int WT = wt_for(P->w);
-  if (P->d == 1) WT == 8 ? launch_spread<T, 1, 8>(P, xs) : launch_spread<T, 1, 16>(P, xs);
-  else if (P->d == 2) WT == 8 ? launch_spread<T, 2, 8>(P, xs) : launch_spread<T, 2, 16>(P, xs);
-  else WT == 8 ? launch_spread<T, 3, 8>(P, xs) : launch_spread<T, 3, 16>(P, xs);
+  if (P->d == 1) launch_spread<T, 1>(P, xs);
+  else if (P->d == 2) launch_spread<T, 2>(P, xs);
+  else launch_spread<T, 3>(P, xs);
 }
 
 template <typename T>
-void interp_dispatch(Plan* P, int64_t n, const DevBuf& cell, const DevBuf& frac, const DevBuf& spn,
-                     const DevBuf& pref, const DevBuf& bs, const double* xs, double* ys,
-                     int add_noise) {
-  const int WT = wt_for(P->w);
-#define GP_I(DD, W) launch_interp<T, DD, W>(P, n, cell, frac, spn, pref, bs, xs, ys, add_noise)
-  if (P->d == 1) { if (WT == 8) GP_I(1, 8); else GP_I(1, 16); }
-  else if (P->d == 2) { if (WT == 8) GP_I(2, 8); else GP_I(2, 16); }
-  else { if (WT == 8) GP_I(3, 8); else GP_I(3, 16); }
-#undef GP_I
+void interp_dispatch(Plan* P, const Records& R, const double* xs, double* ys, int add_noise) {
+  if (P->d == 1) launch_interp<T, 1>(P, R, xs, ys, add_noise);
+  else if (P->d == 2) launch_interp<T, 2>(P, R, xs, ys, add_noise);
+  else launch_interp<T, 3>(P, R, xs, ys, add_noise);
 }
 
 // Forward (sign -1) FFT of every grid pair: active box -> truncated modes.
@@ -569,45 +507,43 @@ void forward_and_mix(Plan* P, const double* xs) {
 void matvec_sorted(Plan* P, const double* xs, double* ys, int add_noise) {
   if (P->precision == GP_FP64) {
     forward_and_mix<double>(P, xs);
-    interp_dispatch<double>(P, P->n, P->cell, P->frac, P->spn, P->pref, P->bin_start, xs, ys,
-                            add_noise);
+    interp_dispatch<double>(P, P->rec, xs, ys, add_noise);
   } else {
     forward_and_mix<float>(P, xs);
-    interp_dispatch<float>(P, P->n, P->cell, P->frac, P->spn, P->pref, P->bin_start, xs, ys,
-                           add_noise);
+    interp_dispatch<float>(P, P->rec, xs, ys, add_noise);
   }
 }
 
 void posterior_sorted(Plan* P, const double* xs, int64_t m, const double* tpts,
                       const double* tsig, const double* tl, double* mu) {
-  DevBuf perm, cell, frac, spn, pref, bs;
+  Records T;
   int oob = 0;
-  build_records_into(P, m, tpts, tsig, tl, perm, cell, frac, spn, pref, bs, &oob);
+  build_records_into(P, m, tpts, tsig, tl, T, &oob);
   if (oob) throw Error{GP_ERANGE, "posterior target outside the plan's box"};
   DevBuf tmp;
   tmp.alloc(m * sizeof(double));
   if (P->precision == GP_FP64) {
     forward_and_mix<double>(P, xs);
-    interp_dispatch<double>(P, m, cell, frac, spn, pref, bs, nullptr, tmp.as<double>(), 0);
+    interp_dispatch<double>(P, T, nullptr, tmp.as<double>(), 0);
   } else {
     forward_and_mix<float>(P, xs);
-    interp_dispatch<float>(P, m, cell, frac, spn, pref, bs, nullptr, tmp.as<double>(), 0);
+    interp_dispatch<float>(P, T, nullptr, tmp.as<double>(), 0);
   }
   hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, P->stream,
-                     m, perm.as<int>(), tmp.as<double>(), mu);
+                     m, T.perm.as<int>(), tmp.as<double>(), mu);
   GP_CHECK_LAUNCH();
   GP_HIP(hipStreamSynchronize(P->stream));
 }
 
 void gather_sorted(Plan* P, const double* xu, double* xs) {
   hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((P->n + 255) / 256)), dim3(256), 0, P->stream,
-                     P->n, P->perm.as<int>(), xu, xs);
+                     P->n, P->rec.perm.as<int>(), xu, xs);
   GP_CHECK_LAUNCH();
 }
 
 void scatter_user(Plan* P, const double* xs, double* xu) {
   hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)((P->n + 255) / 256)), dim3(256), 0,
-                     P->stream, P->n, P->perm.as<int>(), xs, xu);
+                     P->stream, P->n, P->rec.perm.as<int>(), xs, xu);
   GP_CHECK_LAUNCH();
 }
 

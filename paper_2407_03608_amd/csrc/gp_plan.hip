@@ -217,26 +217,53 @@ __global__ void records_kernel(RecArgs a, const double* __restrict__ pts,
   rank[i] = atomicAdd(&counts[bin], 1);
 }
 
+// Scatter the per-point data into bin order and evaluate, once per plan, the
+// window values psi(delta + q), q < w (exponential of semicircle) and the
+// weights w_k(x) = s(x)(2/(pi l'^2))^(d/4) P_k(sigma_p(x)) of eq:Wk with the
+// Lagrange basis in barycentric form on the Chebyshev-Lobatto nodes.
 template <typename T>
-__global__ void scatter_records_kernel(int d, int64_t n, const int* __restrict__ bin_of,
+__global__ void scatter_records_kernel(int d, int64_t n, int w, double beta, int nk, int nkp,
+                                       int rs, const int* __restrict__ bin_of,
                                        const int* __restrict__ rank,
                                        const int* __restrict__ bin_start,
                                        const int* __restrict__ cell_tmp,
                                        const double* __restrict__ frac_tmp,
                                        const double* __restrict__ sp_tmp,
-                                       const double* __restrict__ pf_tmp, int* __restrict__ perm,
-                                       int* __restrict__ cell, T* __restrict__ frac,
-                                       double* __restrict__ spn, double* __restrict__ pref) {
+                                       const double* __restrict__ pf_tmp,
+                                       const double* __restrict__ nodes,
+                                       const double* __restrict__ bary, int* __restrict__ perm,
+                                       int* __restrict__ cell, T* __restrict__ pw) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int64_t pos = (int64_t)bin_start[bin_of[i]] + rank[i];
   perm[pos] = (int)i;
+  T* row = pw + pos * rs;
+  const double tw = 2.0 / w;
   for (int r = 0; r < d; ++r) {
     cell[r * n + pos] = cell_tmp[r * n + i];
-    frac[r * n + pos] = (T)frac_tmp[r * n + i];
+    const double del = frac_tmp[r * n + i];
+    for (int q = 0; q < w; ++q) {
+      const double z = (del + q) * tw;
+      const double u = 1.0 - z * z;
+      row[r * w + q] = (T)(u >= 0.0 ? exp(beta * (sqrt(u) - 1.0)) : 0.0);
+    }
   }
-  spn[pos] = sp_tmp[i];
-  pref[pos] = pf_tmp[i];
+  const double sp = sp_tmp[i], pf = pf_tmp[i];
+  int hit = -1;
+  double den = 0;
+  for (int k = 0; k < nk; ++k) {
+    const double dk = sp - nodes[k];
+    if (dk == 0.0) {
+      hit = k;
+      break;
+    }
+    den += bary[k] / dk;
+  }
+  for (int k = 0; k < nkp; ++k) {
+    double v = 0;
+    if (k < nk) v = hit >= 0 ? (k == hit ? 1.0 : 0.0) : bary[k] / (sp - nodes[k]) / den;
+    row[d * w + k] = (T)(pf * v);
+  }
 }
 
 // Row r of the precomputed step-3 tensor (rem:step3) at |n|^2 = svals[r]:
@@ -274,8 +301,7 @@ __global__ void atab_kernel(int64_t rows, int npk, int nkp, int nk, int nt,
 struct Records;  // fwd (defined in nufft.hip via Plan buffers)
 
 void build_records_into(Plan* P, int64_t n, const double* pts, const double* sig,
-                        const double* l, DevBuf& perm, DevBuf& cell, DevBuf& frac, DevBuf& spn,
-                        DevBuf& pref, DevBuf& bin_start, int* out_of_box) {
+                        const double* l, Records& R, int* out_of_box) {
   hipStream_t s = P->stream;
   const int d = P->d;
   RecArgs a;
@@ -324,26 +350,25 @@ void build_records_into(Plan* P, int64_t n, const double* pts, const double* sig
     acc += hc[b];
   }
   start[P->n_bins] = (int)acc;
-  perm.alloc(n * sizeof(int));
-  cell.alloc(n * d * sizeof(int));
-  frac.alloc(n * d * tsz);
-  spn.alloc(n * sizeof(double));
-  pref.alloc(n * sizeof(double));
-  bin_start.alloc((P->n_bins + 1) * sizeof(int));
-  GP_HIP(hipMemcpyAsync(bin_start.p, start.data(), (P->n_bins + 1) * sizeof(int),
+  R.n = n;
+  R.rs = d * P->w + P->nkp;
+  R.perm.alloc(n * sizeof(int));
+  R.cell.alloc(n * d * sizeof(int));
+  R.pw.alloc((size_t)n * R.rs * tsz);
+  R.bin_start.alloc((P->n_bins + 1) * sizeof(int));
+  GP_HIP(hipMemcpyAsync(R.bin_start.p, start.data(), (P->n_bins + 1) * sizeof(int),
                         hipMemcpyHostToDevice, s));
+#define GP_SCATTER(T)                                                                            \
+  hipLaunchKernelGGL(scatter_records_kernel<T>, dim3(nb), dim3(bs), 0, s, d, n, P->w, P->beta, \
+                     P->nk, P->nkp, R.rs, bin_of.as<int>(), rank.as<int>(),                    \
+                     R.bin_start.as<int>(), cell_tmp.as<int>(), frac_tmp.as<double>(),         \
+                     sp_tmp.as<double>(), pf_tmp.as<double>(), P->nodes_d.as<double>(),        \
+                     P->bary_d.as<double>(), R.perm.as<int>(), R.cell.as<int>(), R.pw.as<T>())
   if (P->precision == GP_FP64)
-    hipLaunchKernelGGL(scatter_records_kernel<double>, dim3(nb), dim3(bs), 0, s, d, n,
-                       bin_of.as<int>(), rank.as<int>(), bin_start.as<int>(), cell_tmp.as<int>(),
-                       frac_tmp.as<double>(), sp_tmp.as<double>(), pf_tmp.as<double>(),
-                       perm.as<int>(), cell.as<int>(), frac.as<double>(), spn.as<double>(),
-                       pref.as<double>());
+    GP_SCATTER(double);
   else
-    hipLaunchKernelGGL(scatter_records_kernel<float>, dim3(nb), dim3(bs), 0, s, d, n,
-                       bin_of.as<int>(), rank.as<int>(), bin_start.as<int>(), cell_tmp.as<int>(),
-                       frac_tmp.as<double>(), sp_tmp.as<double>(), pf_tmp.as<double>(),
-                       perm.as<int>(), cell.as<int>(), frac.as<float>(), spn.as<double>(),
-                       pref.as<double>());
+    GP_SCATTER(float);
+#undef GP_SCATTER
   GP_CHECK_LAUNCH();
   GP_HIP(hipStreamSynchronize(s));
 }
@@ -633,7 +658,7 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
   const int64_t G = P->npair;
   size_t bytes = 0;
   bytes += (size_t)G * (szA + szB + szB2 + szC) * cs;
-  bytes += (size_t)n * (sizeof(int) * (1 + d) + ts * d + 2 * sizeof(double));
+  bytes += (size_t)n * (sizeof(int) * (1 + d) + ts * (d * P->w + P->nk + 1));
   bytes += (size_t)(P->n_bins + 1) * sizeof(int);
   if (P->step3 == 0)
     bytes += (size_t)P->a_rows * (P->nkp * (P->nkp + 1) / 2) * ts + rowmap.size() * sizeof(int);
@@ -781,8 +806,7 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
 
   // ---- points: records and bin sort
   int oob = 0;
-  build_records_into(P, n, pts, sigma, l, P->perm, P->cell, P->frac, P->spn, P->pref,
-                     P->bin_start, &oob);
+  build_records_into(P, n, pts, sigma, l, P->rec, &oob);
   if (oob) throw Error{GP_EDEVICE, "internal: a point's window left the active grid"};
 
   // ---- grids and vectors
