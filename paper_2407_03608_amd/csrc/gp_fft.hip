@@ -1,13 +1,17 @@
-// Batched, pruned 1-D FFT passes for gfx950 (Stockham autosort, LDS resident).
+// Batched, pruned 1-D FFT passes for gfx950 (Stockham autosort).
 //
 // Steps 2 and 4 of the matvec (section 4.2) transform every fine grid along
-// each axis in turn.  One workgroup transforms B sequences of length L: it
-// loads the non-zero input window of each sequence (zero elsewhere) from HBM
-// into LDS, runs the radix-8/4/3/2 stages with each thread holding EPT
-// elements in registers between LDS exchanges, and writes back only the
-// output window that later steps read.  Pruning both windows is what keeps
-// the empty border of the oversampled grid (the points fill only a fraction
-// 2*Delta-omega of the period) and the discarded high frequencies out of HBM.
+// each axis in turn.  A workgroup transforms B sequences of length L.  Each
+// thread keeps EPT elements in registers for the whole transform: the first
+// radix stage loads its inputs straight from HBM (only the non-zero input
+// window; everything else is zero), the last stage stores straight to HBM
+// (only the output window later steps read), and the stages in between
+// exchange data through LDS one real component at a time (a padded buffer of
+// L + L/32 reals per sequence, so two workgroups fit on a CU).  With radices
+// up to 32 an 8192-point transform is three stages and two exchanges.
+// Pruning both windows keeps the empty border of the oversampled grid (points
+// fill a fraction 2*Delta-omega of the period) and the discarded high
+// frequencies out of HBM.
 #include "gp_internal.h"
 
 namespace gp {
@@ -84,58 +88,88 @@ template <typename T, typename V> struct Dft<T, V, 8> {
   }
 };
 
-constexpr int next_radix(int rem, int ept) {
-  return (rem % 8 == 0 && ept % 8 == 0)   ? 8
-         : (rem % 4 == 0 && ept % 4 == 0) ? 4
-         : (rem % 2 == 0 && ept % 2 == 0) ? 2
-         : (rem % 3 == 0 && ept % 3 == 0) ? 3
-                                          : 0;
+// ------------------------------------------------------------ constants ----
+constexpr double kPiC = 3.14159265358979323846264338327950288;
+__host__ __device__ constexpr double taylor_sin(double r) {
+  double t = r, s = r;
+  for (int i = 1; i < 14; ++i) {
+    t *= -r * r / ((2.0 * i) * (2.0 * i + 1.0));
+    s += t;
+  }
+  return s;
 }
+__host__ __device__ constexpr double taylor_cos(double r) {
+  double t = 1, s = 1;
+  for (int i = 1; i < 14; ++i) {
+    t *= -r * r / ((2.0 * i - 1.0) * (2.0 * i));
+    s += t;
+  }
+  return s;
+}
+// cos(2 pi a / b), reduced to |angle - n pi/2| <= pi/4 before the series
+__host__ __device__ constexpr double cos2pi(int a, int b) {
+  a = ((a % b) + b) % b;
+  const int n = (8 * a + b) / (2 * b);
+  const double r = kPiC * (4.0 * a - (double)n * b) / (2.0 * b);
+  return (n & 3) == 0 ? taylor_cos(r) : (n & 3) == 1 ? -taylor_sin(r) : (n & 3) == 2 ? -taylor_cos(r) : taylor_sin(r);
+}
+__host__ __device__ constexpr double sin2pi(int a, int b) { return cos2pi(4 * a - b, 4 * b); }
 
-// One Stockham stage: butterflies j = jt + TPT*u, k = j mod Ls,
-// inputs X[j + m L/R], twiddle exp(s 2 pi i k m / (Ls R)), outputs
-// Y[(j - k) R + k + q Ls].  tw[i] = exp(-2 pi i i / L).
-template <typename T, typename V, int L, int EPT, int R, int Ls>
-__device__ __forceinline__ void stage(V* buf, int jt, const V* __restrict__ tw, int s) {
-  constexpr int TPT = L / EPT;
-  constexpr int NB = EPT / R;
-  V v[EPT];
-#pragma unroll
-  for (int u = 0; u < NB; ++u) {
-    const int j = jt + TPT * u;
-    const int k = j % Ls;
-#pragma unroll
-    for (int m = 0; m < R; ++m) v[u * R + m] = buf[j + m * (L / R)];
-    if (Ls > 1) {
-#pragma unroll
-      for (int m = 1; m < R; ++m) {
-        V t = tw[k * m * (L / (Ls * R))];
-        if (s > 0) t.y = -t.y;
-        v[u * R + m] = cmul(v[u * R + m], t);
-      }
+// ------------------------------------------------------- small DFTs ----
+// y_q = sum_m x_m exp(s 2 pi i q m / R), in place; composite sizes split as
+// R = R1 * R2 (m = m2 R1 + m1, q = q1 R2 + q2) with compile-time twiddles.
+template <typename T, typename V, int R> struct Dft;
+
+template <typename T, typename V, int R1, int R2, int I>
+__device__ __forceinline__ void comp_twiddle(V* z, int s) {
+  if constexpr (I < R1 * R2) {
+    constexpr int m1 = I / R2, q2 = I % R2;
+    if constexpr ((m1 * q2) % (R1 * R2) != 0) {
+      constexpr double c = cos2pi(m1 * q2, R1 * R2), sn = sin2pi(m1 * q2, R1 * R2);
+      z[I] = cmul(z[I], V{T(c), T(s) * T(sn)});
     }
-    Dft<T, V, R>::run(v + u * R, s);
+    comp_twiddle<T, V, R1, R2, I + 1>(z, s);
   }
-  __syncthreads();
-#pragma unroll
-  for (int u = 0; u < NB; ++u) {
-    const int j = jt + TPT * u;
-    const int k = j % Ls;
-#pragma unroll
-    for (int q = 0; q < R; ++q) buf[(j - k) * R + k + q * Ls] = v[u * R + q];
-  }
-  __syncthreads();
 }
 
-template <typename T, typename V, int L, int EPT, int Ls>
-__device__ __forceinline__ void run_stages(V* buf, int jt, const V* __restrict__ tw, int s) {
-  if constexpr (Ls < L) {
-    constexpr int R = next_radix(L / Ls, EPT);
-    static_assert(R > 0, "unsupported FFT length");
-    stage<T, V, L, EPT, R, Ls>(buf, jt, tw, s);
-    run_stages<T, V, L, EPT, Ls * R>(buf, jt, tw, s);
+template <typename T, typename V, int R1, int R2> struct DftComp {
+  __device__ __forceinline__ static void run(V* x, int s) {
+    V z[R1 * R2];
+#pragma unroll
+    for (int m1 = 0; m1 < R1; ++m1) {
+      V t[R2];
+#pragma unroll
+      for (int m2 = 0; m2 < R2; ++m2) t[m2] = x[m2 * R1 + m1];
+      Dft<T, V, R2>::run(t, s);
+#pragma unroll
+      for (int q2 = 0; q2 < R2; ++q2) z[m1 * R2 + q2] = t[q2];
+    }
+    comp_twiddle<T, V, R1, R2, 0>(z, s);
+#pragma unroll
+    for (int q2 = 0; q2 < R2; ++q2) {
+      V t[R1];
+#pragma unroll
+      for (int m1 = 0; m1 < R1; ++m1) t[m1] = z[m1 * R2 + q2];
+      Dft<T, V, R1>::run(t, s);
+#pragma unroll
+      for (int q1 = 0; q1 < R1; ++q1) x[q1 * R2 + q2] = t[q1];
+    }
   }
+};
+template <typename T, typename V> struct Dft<T, V, 16> : DftComp<T, V, 4, 4> {};
+template <typename T, typename V> struct Dft<T, V, 32> : DftComp<T, V, 8, 4> {};
+
+constexpr int next_radix(int rem, int ept) {
+  return (rem % 32 == 0 && ept % 32 == 0)   ? 32
+         : (rem % 16 == 0 && ept % 16 == 0) ? 16
+         : (rem % 8 == 0 && ept % 8 == 0)   ? 8
+         : (rem % 4 == 0 && ept % 4 == 0)   ? 4
+         : (rem % 2 == 0 && ept % 2 == 0)   ? 2
+         : (rem % 3 == 0 && ept % 3 == 0)   ? 3
+                                            : 0;
 }
+
+__device__ __forceinline__ int lpad(int p) { return p + (p >> 5); }
 
 struct KParams {
   int64_t ntrans, inner, in_os, out_os;
@@ -144,6 +178,88 @@ struct KParams {
   int tw4_at_load;
 };
 
+// Stage with sub-transform length Ls and radix R on the registers v:
+// butterfly j = jt + TPT u (u < EPT/R), k = j mod Ls, inputs v[u R + m] =
+// X[j + m L/R], twiddle exp(s 2 pi i k m / (Ls R)) (one table load, powers by
+// recurrence), outputs Y[(j - k) R + k + q Ls].  Then either exchange through
+// LDS into the next stage's inputs or, on the last stage, store.
+template <typename T, typename V, int L, int EPT, int Ls>
+__device__ __forceinline__ void stages(V (&v)[EPT], T* __restrict__ buf, int jt,
+                                       const V* __restrict__ tw, int s, bool act, V* dst,
+                                       int64_t dstride, const KParams& p, const V* tw4,
+                                       int64_t row4) {
+  constexpr int TPT = L / EPT;
+  constexpr int R = next_radix(L / Ls, EPT);
+  static_assert(R > 0, "unsupported FFT length");
+  constexpr int NB = EPT / R;
+  if constexpr (Ls > 1) {
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int j = jt + TPT * u;
+      const int k = j % Ls;
+      V base = tw[k * (L / (Ls * R))];
+      if (s > 0) base.y = -base.y;
+      V wm = base;
+#pragma unroll
+      for (int m = 1; m < R; ++m) {
+        v[u * R + m] = cmul(v[u * R + m], wm);
+        if (m + 1 < R) wm = cmul(wm, base);
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < NB; ++u) Dft<T, V, R>::run(v + u * R, s);
+  if constexpr (Ls * R < L) {
+    constexpr int R2 = next_radix(L / (Ls * R), EPT);
+    static_assert(R2 > 0, "unsupported FFT length");
+    constexpr int NB2 = EPT / R2;
+#pragma unroll
+    for (int comp = 0; comp < 2; ++comp) {
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        const int j = jt + TPT * u;
+        const int k = j % Ls;
+#pragma unroll
+        for (int q = 0; q < R; ++q) buf[lpad((j - k) * R + k + q * Ls)] = comp ? v[u * R + q].y : v[u * R + q].x;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < NB2; ++u) {
+        const int j = jt + TPT * u;
+#pragma unroll
+        for (int m = 0; m < R2; ++m) {
+          const T val = buf[lpad(j + m * (L / R2))];
+          if (comp) v[u * R2 + m].y = val; else v[u * R2 + m].x = val;
+        }
+      }
+      __syncthreads();
+    }
+    stages<T, V, L, EPT, Ls * R>(v, buf, jt, tw, s, act, dst, dstride, p, tw4, row4);
+  } else {
+    // last stage: k = j, outputs at j + q L/R
+    if (!act) return;
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int j = jt + TPT * u;
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int pos = j + q * (L / R);
+        int i = pos - p.out_start;
+        if (i < 0) i += L;
+        if (i < p.n_out) {
+          V val = v[u * R + q];
+          if (tw4 != nullptr && !p.tw4_at_load) {
+            V wv = tw4[((int64_t)pos * row4) % p.L4];
+            if (s > 0) wv.y = -wv.y;
+            val = cmul(val, wv);
+          }
+          dst[(int64_t)i * dstride] = val;
+        }
+      }
+    }
+  }
+}
+
 template <typename T, int L, int EPT, int B>
 __global__ __launch_bounds__(B*(L / EPT)) void fft_pass_kernel(
     const typename V2<T>::type* __restrict__ in, typename V2<T>::type* __restrict__ out,
@@ -151,8 +267,8 @@ __global__ __launch_bounds__(B*(L / EPT)) void fft_pass_kernel(
     KParams p) {
   using V = typename V2<T>::type;
   constexpr int TPT = L / EPT;
-  constexpr int NTHR = B * TPT;
-  __shared__ V buf[B * L];
+  constexpr int LP = L + L / 32;
+  __shared__ T buf[B * LP];
   // Workgroups go to the 8 XCDs round-robin by id.  For strided (column)
   // passes, give each XCD a contiguous range of transforms so neighbouring
   // columns, which share cache lines, run on the same XCD (same L2).
@@ -162,74 +278,52 @@ __global__ __launch_bounds__(B*(L / EPT)) void fft_pass_kernel(
     const int64_t x = bid % 8, slot = bid / 8;
     bid = x < r ? x * (q + 1) + slot : r * (q + 1) + (x - r) * q + slot;
   }
-  const int64_t t0 = bid * B;
-
-  for (int e = threadIdx.x; e < B * L; e += NTHR) {
-    int b, pos;
-    if (p.inner == 1) {
-      b = e / L;
-      pos = e % L;
-    } else {
-      pos = e / B;
-      b = e % B;
-    }
-    const int64_t t = t0 + b;
-    V v = V{T(0), T(0)};
-    if (t < p.ntrans) {
+  int b, jt;
+  if (p.inner == 1) {
+    b = threadIdx.x / TPT;
+    jt = threadIdx.x % TPT;
+  } else {
+    b = threadIdx.x % B;
+    jt = threadIdx.x / B;
+  }
+  const int64_t t = bid * B + b;
+  const bool act = t < p.ntrans;
+  const int64_t o = act ? t / p.inner : 0, c = act ? t - o * p.inner : 0;
+  const V* src = in + o * p.in_os + c;
+  V* dst = out + o * p.out_os + c;
+  const int64_t row4 = tw4 != nullptr ? o % p.tw4_mod : 0;
+  constexpr int R1 = next_radix(L, EPT);
+  constexpr int NB1 = EPT / R1;
+  V v[EPT];
+#pragma unroll
+  for (int u = 0; u < NB1; ++u) {
+    const int j = jt + TPT * u;
+#pragma unroll
+    for (int m = 0; m < R1; ++m) {
+      const int pos = j + m * (L / R1);
       int i = pos - p.in_start;
       if (i < 0) i += L;
-      if (i < p.n_in) {
-        const int64_t o = t / p.inner, c = t - o * p.inner;
-        v = in[o * p.in_os + (int64_t)i * p.inner + c];
+      V val = V{T(0), T(0)};
+      if (act && i < p.n_in) {
+        val = src[(int64_t)i * p.inner];
         if (tw4 != nullptr && p.tw4_at_load) {
-          const int64_t row = o % p.tw4_mod;
-          V w = tw4[((int64_t)pos * row) % p.L4];
-          if (p.sign > 0) w.y = -w.y;
-          v = cmul(v, w);
+          V wv = tw4[((int64_t)pos * row4) % p.L4];
+          if (p.sign > 0) wv.y = -wv.y;
+          val = cmul(val, wv);
         }
       }
+      v[u * R1 + m] = val;
     }
-    buf[b * L + pos] = v;
   }
-  __syncthreads();
-
-  {
-    const int b = threadIdx.x / TPT;
-    const int jt = threadIdx.x % TPT;
-    run_stages<T, V, L, EPT, 1>(buf + b * L, jt, tw, p.sign);
-  }
-
-  for (int e = threadIdx.x; e < B * p.n_out; e += NTHR) {
-    int b, i;
-    if (p.inner == 1) {
-      b = e / p.n_out;
-      i = e - b * p.n_out;
-    } else {
-      i = e / B;
-      b = e - i * B;
-    }
-    const int64_t t = t0 + b;
-    if (t >= p.ntrans) continue;
-    int pos = p.out_start + i;
-    if (pos >= L) pos -= L;
-    V v = buf[b * L + pos];
-    const int64_t o = t / p.inner, c = t - o * p.inner;
-    if (tw4 != nullptr && !p.tw4_at_load) {
-      const int64_t row = o % p.tw4_mod;
-      V w = tw4[((int64_t)pos * row) % p.L4];
-      if (p.sign > 0) w.y = -w.y;
-      v = cmul(v, w);
-    }
-    out[o * p.out_os + (int64_t)i * p.inner + c] = v;
-  }
+  stages<T, V, L, EPT, 1>(v, buf + b * LP, jt, tw, p.sign, act, dst, p.inner, p, tw4, row4);
 }
 
-constexpr int ept_for(int L) { return (L % 3 == 0) ? 24 : 8; }
+constexpr int ept_for(int L) { return (L % 3 == 0) ? (L < 24 ? L : 24) : (L < 32 ? L : 32); }
 constexpr int batch_for(int L, int elem_bytes) {
   int tpt = L / ept_for(L);
   int b = 256 / tpt;
   if (b < 1) b = 1;
-  int cap = (64 * 1024) / (L * elem_bytes);
+  int cap = (80 * 1024) / ((L + L / 32) * elem_bytes);
   if (cap < 1) cap = 1;
   return b < cap ? b : cap;
 }
@@ -238,7 +332,7 @@ template <typename T, int L>
 void launch_len(const FftPass& q, const void* in, void* out, const void* tw, hipStream_t s) {
   using V = typename V2<T>::type;
   constexpr int EPT = ept_for(L);
-  constexpr int B = batch_for(L, (int)sizeof(V));
+  constexpr int B = batch_for(L, (int)sizeof(T));
   KParams p;
   p.ntrans = q.n_outer * q.inner;
   p.inner = q.inner;
