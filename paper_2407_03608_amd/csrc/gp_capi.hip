@@ -1,6 +1,8 @@
 // C ABI of gpnufft (declarations and contracts in include/gpnufft.h).
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -251,6 +253,13 @@ int gp_cg_solve_refined(gp_plan_t hin, gp_plan_t hout, const double* y, double* 
       gather_sorted(Po, r, Vo + 7 * n);
       const double rr = dot_sorted(Po, Vo + 7 * n, Vo + 7 * n, n);
       rel = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+      if (const char* e = std::getenv("GPNUFFT_PROGRESS")) {
+        if (std::atoi(e) > 0) {
+          std::fprintf(stderr, "[gpnufft] refine pass=%d inner_iters=%d outer_rel_res=%.3e\n", passes,
+                       total, rel);
+          std::fflush(stderr);
+        }
+      }
       if (rel <= tol || passes >= max_refine || total >= max_iter) break;
       // inner solve A_inner d = r
       const double itol = std::max(tol / std::max(rel, 1e-300), inner_tol);

@@ -5,6 +5,8 @@
 // lengths alpha, beta stay on the device; the host reads ||r||^2 once per
 // iteration for the stopping test.
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 
 #include "gp_internal.h"
 
@@ -183,6 +185,9 @@ int cg_solve_sorted(Plan* P, const double* b, double* x, bool x_zero, double tol
     return GP_OK;
   }
   const double stop2 = tol * tol * bb;
+  // optional progress lines on stderr every GPNUFFT_PROGRESS iterations
+  int progress = 0;
+  if (const char* e = std::getenv("GPNUFFT_PROGRESS")) progress = std::atoi(e);
   int it = 0;
   while (rr > stop2 && it < max_iter) {
     ++it;
@@ -210,6 +215,10 @@ int cg_solve_sorted(Plan* P, const double* b, double* x, bool x_zero, double tol
     }
     rr = read_slot(P, sc, 2);
     if (!std::isfinite(rr)) throw Error{GP_EDEVICE, "CG breakdown: non-finite residual"};
+    if (progress > 0 && it % progress == 0) {
+      std::fprintf(stderr, "[gpnufft] cg it=%d rel_res=%.3e\n", it, std::sqrt(rr / bb));
+      std::fflush(stderr);
+    }
   }
   *iters = it;
   *rel_res = std::sqrt(rr / bb);

@@ -1,0 +1,91 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py times.
+
+The oracle cannot form K~ alpha for 1e6-1e7 points, but with a sparse alpha
+(a few non-zeros) every output is a short sum of K~ entries, which the oracle
+evaluates one by one (theta-sum form of eq:Ktilde).  Properties that hold at any
+size (symmetry of K~ = adjointness of the two NUFFTs, positive semidefiniteness,
+fp32 vs fp64 agreement) are checked with dense vectors.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2407_03608_amd import inputs
+from tests.gpu_common import cuda, host, oracle_params, rel, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gp():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2407_03608_amd import gp as g
+    g.load()
+    O.build()
+    return g
+
+
+def _sparse_check(gp, P, prob, n_nz=3, n_near=6, n_far=3, seed=0, bar=1e-6):
+    rng = np.random.default_rng(seed)
+    nz = rng.choice(prob.n, size=n_nz, replace=False)
+    a = np.zeros(prob.n)
+    a[nz] = rng.standard_normal(n_nz)
+    got = host(P.matvec(cuda(a)))
+    # outputs: the non-zeros, their nearest neighbours, a few random points
+    samp = list(nz)
+    for j in nz:
+        d2 = ((prob.x - prob.x[j]) ** 2).sum(1)
+        d2[j] = np.inf
+        samp += list(np.argpartition(d2, n_near)[:n_near])
+    samp += list(rng.choice(prob.n, size=n_far, replace=False))
+    samp = np.array(samp)
+    K = O.ktilde_entries(oracle_params(P.info()), prob.x[samp], prob.sigma[samp], prob.l[samp],
+                         prob.x[nz], prob.sigma[nz], prob.l[nz])
+    ref = K @ a[nz]
+    e = rel(got[samp], ref)
+    say(f"  sampled outputs ({len(samp)}) vs oracle K~ entries: {e:.3e}")
+    assert e <= bar
+    return e
+
+
+def _properties(gp, P, n, bar_sym):
+    rng = np.random.default_rng(1)
+    u, v = rng.standard_normal(n), rng.standard_normal(n)
+    ku = host(P.matvec(cuda(u)))
+    kv = host(P.matvec(cuda(v)))
+    s1, s2 = float(u @ kv), float(ku @ v)
+    say(f"  <u,Kv>={s1:.6e} <Ku,v>={s2:.6e}")
+    assert abs(s1 - s2) <= bar_sym * (np.linalg.norm(u) * np.linalg.norm(kv))
+    assert float(v @ kv) > 0 and float(u @ ku) > 0
+    return ku
+
+
+def test_matern_2d_full_size_fp64_and_fp32(gp):
+    prob = inputs.matern_2d()
+    say("case matern_2d N=1e6 fp64 tol 1e-8")
+    P64 = gp.Plan(cuda(prob.x), cuda(prob.sigma), cuda(prob.l), prob.nu, prob.eta, 1e-8)
+    info = P64.info()
+    say("  plan", {k: info[k] for k in ("n_sigma", "n_t", "dw", "M", "nf", "w", "na", "n_pairs")})
+    assert info["nf"][0] == 8192 and info["M"] == 2047
+    _sparse_check(gp, P64, prob, bar=1e-6)
+    k64 = _properties(gp, P64, prob.n, 1e-10)
+    say("case matern_2d N=1e6 fp32-bulk tol 1e-4 (shared dw, M)")
+    P32 = gp.Plan(cuda(prob.x), cuda(prob.sigma), cuda(prob.l), prob.nu, prob.eta, 1e-4,
+                  precision=gp.GP_FP32_BULK, dw=info["dw"], M=info["M"])
+    _sparse_check(gp, P32, prob, bar=2e-4)
+    k32 = _properties(gp, P32, prob.n, 1e-5)
+    # same problem, fp32 operator vs fp64 operator (different N_sigma, N_t, w): stated
+    say(f"  fp32 vs fp64 operator on the same vector: {rel(k32, k64):.3e}")
+    assert rel(k32, k64) < 1e-3
+
+
+def test_matern_3d_full_size_fp32(gp):
+    prob = inputs.matern_3d()
+    say("case matern_3d N=1e7 fp32-bulk tol 1e-4")
+    P = gp.Plan(cuda(prob.x), cuda(prob.sigma), cuda(prob.l), prob.nu, prob.eta, 1e-4,
+                precision=gp.GP_FP32_BULK)
+    info = P.info()
+    say("  plan", {k: info[k] for k in ("n_sigma", "n_t", "dw", "M", "nf", "w", "na", "n_pairs", "device_bytes")})
+    _sparse_check(gp, P, prob, bar=2e-4)
+    _properties(gp, P, prob.n, 1e-5)
