@@ -74,6 +74,12 @@ typedef struct {
   double box_lo[3], box_hi[3];
   double l_lo, l_hi;        /* widen the length-scale range (posterior targets); 0 = unused */
   size_t max_device_bytes;  /* admission limit for the plan's device memory; 0 = none */
+  int spread;               /* type-1 spreading: 0 = each thread owns grid cells and sums
+                               in registers (deterministic, default); 1 = per-(point, row)
+                               work items with LDS atomics */
+  int interp;               /* type-2 interpolation: 0 = the bin's tile plus halo staged in
+                               LDS, (point, window row, pair) items (default); 1 = one thread
+                               per point reading its window through the caches */
   int step3;                /* step 3 of section 4.2 (rem:step3): 0 = precomputed tensor
                                A_k'k, stored once per distinct |n|^2 (default); 1 = direct
                                sum over the t nodes at every mode */
@@ -105,6 +111,8 @@ typedef struct {
   double pred_tail;         /* predicted spectral-tail error of the Fourier box, relative */
   int m_capped;             /* 1 if M was limited by M_cap */
   int step3;                /* variant of step 3 in use (see gp_opts.step3) */
+  int spread;               /* spreading variant in use (see gp_opts.spread) */
+  int interp;               /* interpolation variant in use (see gp_opts.interp) */
   int64_t a_rows;           /* rows of the precomputed A table (distinct |n|^2) */
 } gp_plan_params;
 

@@ -164,6 +164,8 @@ int gp_plan_info(gp_plan_t h, gp_plan_params* o) {
     o->pred_tail = P.pred_tail;
     o->m_capped = P.m_capped;
     o->step3 = P.step3;
+    o->spread = P.spread_owner ? 0 : 1;
+    o->interp = P.interp_gather ? 1 : 0;
     o->a_rows = P.a_rows;
     return GP_OK;
   });

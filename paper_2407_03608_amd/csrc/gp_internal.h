@@ -127,6 +127,8 @@ struct Plan {
   DevBuf etab;                // T [nt][nk][M+1]: exp(-tau_kj n^2) for dims >= 1
   DevBuf vtd;                 // T [nt] v~_j
   int step3 = 0;              // 0: radial precomputed A, 1: direct t-sum
+  int spread_owner = 1;       // 1: owner-computes spreading (no atomics), 0: LDS-atomic items
+  int interp_gather = 0;      // 1: one thread per point from cache, 0: LDS-staged tiles
   int64_t a_rows = 0;         // distinct |n|^2 values (rows of A)
   int nkp = 0;                // table width: nk rounded up to even
   DevBuf atab;                // T [a_rows][nkp(nkp+1)/2] upper triangle of A_k'k(|n|^2)

@@ -164,53 +164,73 @@ __global__ __launch_bounds__(kThreads) void mode_radial_kernel(
       first_nz = r;
       break;
     }
+  // Sign patterns are processed two at a time so that one pass over the row of
+  // A serves both (the row is the dominant read of this kernel).
   const int npat = 1 << (a.d - 1);
-  for (int pat = 0; pat < npat; ++pat) {
-    int64_t nv[3] = {0, 0, 0}, nvc[3] = {0, 0, 0};
-    bool keep = true;
-    for (int r = 0; r < a.d; ++r) {
-      const int neg = r == 0 ? 0 : ((pat >> (r - 1)) & 1);
-      if (neg && (an[r] == 0 || r == first_nz)) keep = false;  // duplicate pattern
-      nv[r] = neg ? -an[r] : an[r];
-      nvc[r] = -nv[r];
-    }
-    if (!keep) continue;
-    const int64_t s0 = radial_store(a, nv), s1 = radial_store(a, nvc);
-    V b[NK];
+  for (int pg = 0; pg < npat; pg += 2) {
+    bool keep[2];
+    int64_t st0[2], st1[2];
 #pragma unroll
-    for (int g = 0; g < NK / 2; ++g) {
-      V z = V{T(0), T(0)}, zc = V{T(0), T(0)};
-      if (g < a.npair) {
-        z = C[g * a.pair_stride + s0];
-        zc = C[g * a.pair_stride + s1];
+    for (int h = 0; h < 2; ++h) {
+      const int pat = pg + h;
+      keep[h] = pat < npat;
+      int64_t nv[3] = {0, 0, 0}, nvc[3] = {0, 0, 0};
+      for (int r = 0; r < a.d; ++r) {
+        const int neg = r == 0 ? 0 : ((pat >> (r - 1)) & 1);
+        if (neg && (an[r] == 0 || r == first_nz)) keep[h] = false;  // duplicate pattern
+        nv[r] = neg ? -an[r] : an[r];
+        nvc[r] = -nv[r];
       }
-      b[2 * g] = V{T(0.5) * (z.x + zc.x) * D, T(0.5) * (z.y - zc.y) * D};
-      b[2 * g + 1] = V{T(0.5) * (z.y + zc.y) * D, T(-0.5) * (z.x - zc.x) * D};
+      st0[h] = keep[h] ? radial_store(a, nv) : 0;
+      st1[h] = keep[h] ? radial_store(a, nvc) : 0;
     }
-    V acc[NK];
+    if (!keep[0] && !keep[1]) continue;
+    V b[2][NK];
 #pragma unroll
-    for (int k = 0; k < NK; ++k) acc[k] = V{T(0), T(0)};
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int g = 0; g < NK / 2; ++g) {
+        V z = V{T(0), T(0)}, zc = V{T(0), T(0)};
+        if (keep[h] && g < a.npair) {
+          z = C[g * a.pair_stride + st0[h]];
+          zc = C[g * a.pair_stride + st1[h]];
+        }
+        b[h][2 * g] = V{T(0.5) * (z.x + zc.x) * D, T(0.5) * (z.y - zc.y) * D};
+        b[h][2 * g + 1] = V{T(0.5) * (z.y + zc.y) * D, T(-0.5) * (z.x - zc.x) * D};
+      }
+    V acc[2][NK];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int k = 0; k < NK; ++k) acc[h][k] = V{T(0), T(0)};
     int p = 0;
 #pragma unroll
     for (int k1 = 0; k1 < NK; ++k1) {
 #pragma unroll
       for (int k2 = k1; k2 < NK; ++k2) {
         const T av = Ar[p++];
-        acc[k1].x += av * b[k2].x;
-        acc[k1].y += av * b[k2].y;
-        if (k2 != k1) {
-          acc[k2].x += av * b[k1].x;
-          acc[k2].y += av * b[k1].y;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          acc[h][k1].x += av * b[h][k2].x;
+          acc[h][k1].y += av * b[h][k2].y;
+          if (k2 != k1) {
+            acc[h][k2].x += av * b[h][k1].x;
+            acc[h][k2].y += av * b[h][k1].y;
+          }
         }
       }
     }
 #pragma unroll
-    for (int g = 0; g < NK / 2; ++g) {
-      if (g >= a.npair) break;
-      const V pp = V{acc[2 * g].x * D, acc[2 * g].y * D};
-      const V qq = V{acc[2 * g + 1].x * D, acc[2 * g + 1].y * D};
-      C[g * a.pair_stride + s0] = V{pp.x - qq.y, pp.y + qq.x};
-      if (s1 != s0) C[g * a.pair_stride + s1] = V{pp.x + qq.y, -pp.y + qq.x};
+    for (int h = 0; h < 2; ++h) {
+      if (!keep[h]) continue;
+#pragma unroll
+      for (int g = 0; g < NK / 2; ++g) {
+        if (g >= a.npair) break;
+        const V pp = V{acc[h][2 * g].x * D, acc[h][2 * g].y * D};
+        const V qq = V{acc[h][2 * g + 1].x * D, acc[h][2 * g + 1].y * D};
+        C[g * a.pair_stride + st0[h]] = V{pp.x - qq.y, pp.y + qq.x};
+        if (st1[h] != st0[h]) C[g * a.pair_stride + st1[h]] = V{pp.x + qq.y, -pp.y + qq.x};
+      }
     }
   }
 }

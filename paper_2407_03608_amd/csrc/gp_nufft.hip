@@ -63,6 +63,124 @@ struct NuArgs {
 // stride so that lanes reading different points hit different banks) and x_i.
 __host__ __device__ constexpr int lds_stride(int rs) { return rs | 1; }
 
+// ---------------------------------------------------------- spread (owner) ----
+// Owner-computes variant: each thread owns CPT cells of the tile and, for every
+// staged source point, adds its contribution to the grid pairs of the chunk in
+// registers when the point's window covers the cell.  No atomics, so the
+// summation order (and the result) is fixed.
+template <typename T, int D, int CPT>
+__global__ __launch_bounds__(kThreads) void spread_owner_kernel(
+    NuArgs a, const double* __restrict__ x, const int* __restrict__ cell,
+    const T* __restrict__ pw, int rs, const int* __restrict__ bin_start,
+    typename V2<T>::type* __restrict__ grid) {
+  using V = typename V2<T>::type;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int tc0 = a.tile[0], tc1 = D > 1 ? a.tile[1] : 1;
+  const int ls = lds_stride(rs);
+  T* s_rec = reinterpret_cast<T*>(smem);          // [kPB][ls]
+  T* s_x = s_rec + kPB * ls;                      // [kPB]
+  int* s_cell = reinterpret_cast<int*>(s_x + kPB);  // [kPB][D]
+
+  int tcoord[3] = {0, 0, 0}, t0[3] = {0, 0, 0};
+  {
+    int64_t tb = blockIdx.x;
+    for (int r = 0; r < D; ++r) {
+      tcoord[r] = (int)(tb % a.nbins[r]);
+      tb /= a.nbins[r];
+      t0[r] = tcoord[r] * a.tile[r];
+    }
+  }
+  // my cells (absolute active-box coordinates)
+  const int tcells = tc0 * tc1 * (D > 2 ? a.tile[2] : 1);
+  int cx[CPT], cy[CPT], cz[CPT];
+  bool mine[CPT];
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    int l = threadIdx.x + c * kThreads;
+    mine[c] = l < tcells;
+    if (!mine[c]) l = 0;
+    cx[c] = t0[0] + l % tc0;
+    l /= tc0;
+    cy[c] = D > 1 ? t0[1] + l % tc1 : 0;
+    cz[c] = D > 2 ? t0[2] + l / tc1 : 0;
+  }
+  V acc[CPT][kGC];
+#pragma unroll
+  for (int c = 0; c < CPT; ++c)
+#pragma unroll
+    for (int g = 0; g < kGC; ++g) acc[c][g] = V{T(0), T(0)};
+
+  const int w = a.w;
+  const int wko = D * w + 2 * a.g0;
+  int nsrc_tot = 1;
+  for (int r = 0; r < D; ++r) nsrc_tot *= a.nsrc;
+  for (int sb = 0; sb < nsrc_tot; ++sb) {
+    int64_t bin = 0, mul = 1;
+    bool ok = true;
+    int q = sb;
+    for (int r = 0; r < D; ++r) {
+      int br = tcoord[r] - (q % a.nsrc);
+      q /= a.nsrc;
+      if (br < 0) ok = false;
+      bin += (int64_t)br * mul;
+      mul *= a.nbins[r];
+    }
+    if (!ok) continue;
+    const int p0 = bin_start[bin], p1 = bin_start[bin + 1];
+    for (int pb = p0; pb < p1; pb += kPB) {
+      const int np = min(kPB, p1 - pb);
+      __syncthreads();
+      for (int e = threadIdx.x; e < np * rs; e += kThreads) {
+        const int p = e / rs;
+        s_rec[p * ls + (e - p * rs)] = pw[(int64_t)pb * rs + e];
+      }
+      if (threadIdx.x < np) {
+        s_x[threadIdx.x] = (T)x[pb + threadIdx.x];
+        for (int r = 0; r < D; ++r) s_cell[threadIdx.x * D + r] = cell[r * a.n + pb + threadIdx.x];
+      }
+      __syncthreads();
+      for (int p = 0; p < np; ++p) {
+        const T* pr = s_rec + p * ls;
+        const int s0 = s_cell[p * D];
+        const int s1 = D > 1 ? s_cell[p * D + 1] : 0;
+        const int s2 = D > 2 ? s_cell[p * D + 2] : 0;
+        const T xa = s_x[p];
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+          const unsigned d0 = (unsigned)(cx[c] - s0);
+          const unsigned d1 = (unsigned)(cy[c] - s1);
+          const unsigned d2 = (unsigned)(cz[c] - s2);
+          bool hit = d0 < (unsigned)w;
+          if (D > 1) hit = hit && d1 < (unsigned)w;
+          if (D > 2) hit = hit && d2 < (unsigned)w;
+          if (hit) {
+            T v = pr[d0] * xa;
+            if (D > 1) v *= pr[w + d1];
+            if (D > 2) v *= pr[2 * w + d2];
+#pragma unroll
+            for (int g = 0; g < kGC; ++g) {
+              if (g < a.gc) {
+                acc[c][g].x += v * pr[wko + 2 * g];
+                acc[c][g].y += v * pr[wko + 2 * g + 1];
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+  // write my cells (the tile is exclusively owned)
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    if (!mine[c]) continue;
+    const int64_t gi = a.grid_off + (int64_t)cx[c] * a.gstride[0] + (int64_t)cy[c] * a.gstride[1] +
+                       (int64_t)cz[c] * a.gstride[2];
+#pragma unroll
+    for (int g = 0; g < kGC; ++g)
+      if (g < a.gc) grid[(int64_t)(a.g0 + g) * a.pair_stride + gi] = acc[c][g];
+  }
+}
+
 // ---------------------------------------------------------------- spread ----
 // One workgroup per tile of the active grid and chunk of complex grids.  The
 // sources are the bins whose points' windows can reach the tile (nsrc per
@@ -177,6 +295,58 @@ __global__ __launch_bounds__(kThreads) void spread_kernel(
   }
 }
 
+// ------------------------------------------------------- interp (gather) ----
+// One thread per point: sums its w^d window of every grid pair straight from
+// the cache hierarchy (points are bin-sorted, so neighbouring threads read
+// overlapping windows) and forms sum_k w_k beta_k (+ eta^2 x_i).
+template <typename T, int D, int WT>
+__global__ __launch_bounds__(kThreads) void interp_gather_kernel(
+    NuArgs a, const typename V2<T>::type* __restrict__ grid, const int* __restrict__ cell,
+    const T* __restrict__ pw, int rs, const double* __restrict__ x, double* __restrict__ y) {
+  using V = typename V2<T>::type;
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= a.n) return;
+  const int w = a.w;
+  const T* pr = pw + i * rs;
+  T p0[WT], p1[WT], p2[WT];
+#pragma unroll
+  for (int q = 0; q < WT; ++q) {
+    p0[q] = q < w ? pr[q] : T(0);
+    p1[q] = (D > 1 && q < w) ? pr[w + q] : T(0);
+    p2[q] = (D > 2 && q < w) ? pr[2 * w + q] : T(0);
+  }
+  const int64_t base = a.grid_off + (int64_t)cell[i] * a.gstride[0] +
+                       (D > 1 ? (int64_t)cell[a.n + i] * a.gstride[1] : 0) +
+                       (D > 2 ? (int64_t)cell[2 * a.n + i] * a.gstride[2] : 0);
+  double out = a.add_noise ? a.eta2 * x[i] : 0.0;
+  const int n1 = D > 1 ? w : 1, n2 = D > 2 ? w : 1;
+  for (int g = 0; g < a.npair; ++g) {
+    const V* gp = grid + (int64_t)g * a.pair_stride + base;
+    T sx = 0, sy = 0;
+    for (int q2 = 0; q2 < n2; ++q2) {
+      for (int q1 = 0; q1 < n1; ++q1) {
+        T wv = T(1);
+        if (D > 1) wv = p1[q1];
+        if (D > 2) wv *= p2[q2];
+        const V* row = gp + (D > 1 ? (int64_t)q1 * a.gstride[1] : 0) + (D > 2 ? (int64_t)q2 * a.gstride[2] : 0);
+        T rx = 0, ry = 0;
+#pragma unroll
+        for (int q0 = 0; q0 < WT; ++q0) {
+          if (q0 < w) {
+            const V v = row[q0];
+            rx += p0[q0] * v.x;
+            ry += p0[q0] * v.y;
+          }
+        }
+        sx += wv * rx;
+        sy += wv * ry;
+      }
+    }
+    out += (double)pr[D * w + 2 * g] * (double)sx + (double)pr[D * w + 2 * g + 1] * (double)sy;
+  }
+  y[i] = out;
+}
+
 // ---------------------------------------------------------------- interp ----
 // One workgroup per bin.  For each chunk of complex grids the bin's tile plus
 // its (w-1) halo is staged in LDS; every (point, grid pair) item sums its
@@ -239,38 +409,37 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(
       s_acc[threadIdx.x] = 0.0;
     }
     __syncthreads();
-    const int nitems = np * a.gc;
+    // items: (point, window row, grid pair); each adds its row's share of
+    // w_2g beta_2g + w_2g+1 beta_2g+1 to the point's accumulator
+    const int nitems = np * cellsw * a.gc;
     for (int it = threadIdx.x; it < nitems; it += kThreads) {
       const int p = it % np;
-      const int g = it / np;
+      const int rest = it / np;
+      const int row = rest % cellsw;
+      const int g = rest / cellsw;
       const T* pr = s_rec + p * ls;
-      const V* tg = tileA + (size_t)g * pcells + s_cell[p * D];
-      T sx = 0, sy = 0;
-      for (int row = 0; row < cellsw; ++row) {
-        T wv = T(1);
-        int off = 0;
-        if (D > 1) {
-          const int q1 = row % w;
-          wv *= pr[w + q1];
-          off += (s_cell[p * D + 1] + q1) * pc0;
-        }
-        if (D > 2) {
-          const int q2 = row / w;
-          wv *= pr[2 * w + q2];
-          off += (s_cell[p * D + 2] + q2) * pc0 * pc1;
-        }
-        const V* tr = tg + off;
-        T rx = 0, ry = 0;
-        for (int q0 = 0; q0 < w; ++q0) {
-          const T ps = pr[q0];
-          const V gv = tr[q0];
-          rx += ps * gv.x;
-          ry += ps * gv.y;
-        }
-        sx += wv * rx;
-        sy += wv * ry;
+      T wv = T(1);
+      int off = s_cell[p * D];
+      if (D > 1) {
+        const int q1 = row % w;
+        wv *= pr[w + q1];
+        off += (s_cell[p * D + 1] + q1) * pc0;
       }
-      const double contrib = (double)pr[wko + 2 * g] * (double)sx + (double)pr[wko + 2 * g + 1] * (double)sy;
+      if (D > 2) {
+        const int q2 = row / w;
+        wv *= pr[2 * w + q2];
+        off += (s_cell[p * D + 2] + q2) * pc0 * pc1;
+      }
+      const V* tr = tileA + (size_t)g * pcells + off;
+      T rx = 0, ry = 0;
+      for (int q0 = 0; q0 < w; ++q0) {
+        const T ps = pr[q0];
+        const V gv = tr[q0];
+        rx += ps * gv.x;
+        ry += ps * gv.y;
+      }
+      const double contrib =
+          (double)wv * ((double)pr[wko + 2 * g] * (double)rx + (double)pr[wko + 2 * g + 1] * (double)ry);
       atomicAdd(&s_acc[p], contrib);
     }
     __syncthreads();
@@ -342,6 +511,29 @@ NuArgs nu_args(const Plan* P) {
   return a;
 }
 
+template <typename T>
+size_t spread_owner_smem(const Plan* P, int rs) {
+  return kPB * (lds_stride(rs) + 1) * sizeof(T) + kPB * P->d * sizeof(int) + 16;
+}
+
+template <typename T, int D, int CPT>
+void launch_spread_owner(Plan* P, const double* xs) {
+  PhaseScope ps(P, PH_SPREAD);
+  NuArgs a = nu_args(P);
+  const Records& R = P->rec;
+  const int gc = std::min(kGC, P->npair);
+  const int nch = (P->npair + gc - 1) / gc;
+  for (int ch = 0; ch < nch; ++ch) {
+    a.g0 = ch * gc;
+    a.gc = std::min(gc, P->npair - a.g0);
+    hipLaunchKernelGGL((spread_owner_kernel<T, D, CPT>), dim3((unsigned)P->n_bins), dim3(kThreads),
+                       spread_owner_smem<T>(P, R.rs), P->stream, a, xs, R.cell.as<int>(),
+                       R.pw.as<T>(), R.rs, R.bin_start.as<int>(),
+                       P->gridA.as<typename V2<T>::type>());
+    GP_CHECK_LAUNCH();
+  }
+}
+
 template <typename T, int D>
 void launch_spread(Plan* P, const double* xs) {
   PhaseScope ps(P, PH_SPREAD);
@@ -361,12 +553,25 @@ void launch_spread(Plan* P, const double* xs) {
   }
 }
 
+// Dynamic LDS above 64 KB needs an explicit per-kernel opt-in.
+constexpr size_t kSmemBig = 150 * 1024;
+template <typename K>
+void allow_big_lds(K kernel) {
+  static bool done = false;
+  if (!done) {
+    GP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmemBig));
+    done = true;
+  }
+}
+
 template <typename T, int D>
 void launch_interp(Plan* P, const Records& R, const double* xs, double* ys, int add_noise) {
   PhaseScope ps(P, PH_INTERP);
   NuArgs a = nu_args(P);
   a.n = R.n;
   a.add_noise = add_noise;
+  allow_big_lds(interp_kernel<T, D>);
   int gc = std::min(kGC, P->npair);
   while (gc > 1 && interp_smem<T>(P, gc, R.rs) > kSmemCap) --gc;
   const int nch = (P->npair + gc - 1) / gc;
@@ -386,13 +591,44 @@ void launch_interp(Plan* P, const Records& R, const double* xs, double* ys, int 
 
 template <typename T>
 void spread_dispatch(Plan* P, const double* xs) {
+  const int tcells = P->tile[0] * P->tile[1] * P->tile[2];
+  if (P->spread_owner && tcells <= 2 * kThreads) {
+    const bool two = tcells > kThreads;
+    if (P->d == 1) two ? launch_spread_owner<T, 1, 2>(P, xs) : launch_spread_owner<T, 1, 1>(P, xs);
+    else if (P->d == 2) two ? launch_spread_owner<T, 2, 2>(P, xs) : launch_spread_owner<T, 2, 1>(P, xs);
+    else two ? launch_spread_owner<T, 3, 2>(P, xs) : launch_spread_owner<T, 3, 1>(P, xs);
+    return;
+  }
   if (P->d == 1) launch_spread<T, 1>(P, xs);
   else if (P->d == 2) launch_spread<T, 2>(P, xs);
   else launch_spread<T, 3>(P, xs);
 }
 
+template <typename T, int D, int WT>
+void launch_interp_gather(Plan* P, const Records& R, const double* xs, double* ys, int add_noise) {
+  PhaseScope ps(P, PH_INTERP);
+  NuArgs a = nu_args(P);
+  a.n = R.n;
+  a.add_noise = add_noise;
+  const DevBuf& g = P->fourstep ? P->gridC : P->gridA;
+  hipLaunchKernelGGL((interp_gather_kernel<T, D, WT>), dim3((unsigned)((R.n + kThreads - 1) / kThreads)),
+                     dim3(kThreads), 0, P->stream, a, g.as<typename V2<T>::type>(), R.cell.as<int>(),
+                     R.pw.as<T>(), R.rs, xs, ys);
+  GP_CHECK_LAUNCH();
+}
+
 template <typename T>
 void interp_dispatch(Plan* P, const Records& R, const double* xs, double* ys, int add_noise) {
+  if (P->interp_gather) {  // cache-gather variant
+    const bool big = P->w > 8;
+#define GP_IG(DD) big ? launch_interp_gather<T, DD, 16>(P, R, xs, ys, add_noise) \
+                      : launch_interp_gather<T, DD, 8>(P, R, xs, ys, add_noise)
+    if (P->d == 1) GP_IG(1);
+    else if (P->d == 2) GP_IG(2);
+    else GP_IG(3);
+#undef GP_IG
+    return;
+  }
   if (P->d == 1) launch_interp<T, 1>(P, R, xs, ys, add_noise);
   else if (P->d == 2) launch_interp<T, 2>(P, R, xs, ys, add_noise);
   else launch_interp<T, 3>(P, R, xs, ys, add_noise);

@@ -607,6 +607,8 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
 
   // ---- step 3 variant; radial rows of the precomputed tensor
   P->step3 = opts.step3 ? 1 : 0;
+  P->spread_owner = opts.spread ? 0 : 1;
+  P->interp_gather = opts.interp ? 1 : 0;
   P->nkp = P->nk + (P->nk & 1);
   std::vector<double> svals;
   std::vector<int> rowmap;

@@ -52,6 +52,8 @@ class GpOpts(ctypes.Structure):
         ("l_lo", _c_d),
         ("l_hi", _c_d),
         ("max_device_bytes", _c_sz),
+        ("spread", _c_i),
+        ("interp", _c_i),
         ("step3", _c_i),
         ("stream", _c_p),
     ]
@@ -86,6 +88,8 @@ class GpPlanParams(ctypes.Structure):
         ("pred_tail", _c_d),
         ("m_capped", _c_i),
         ("step3", _c_i),
+        ("spread", _c_i),
+        ("interp", _c_i),
         ("a_rows", _c_i64),
     ]
 

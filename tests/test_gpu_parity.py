@@ -76,6 +76,24 @@ def test_step3_variants_agree(gp, d, M, prec):
     assert rel(got_r, got_d) < (1e-11 if prec == 0 else 1e-5)
 
 
+@pytest.mark.parametrize("d,M,prec", [(1, 150, 0), (2, 24, 0), (3, 8, 0), (2, 24, 1), (3, 8, 1)])
+def test_spread_and_interp_variants(gp, d, M, prec):
+    """Owner-computes / LDS-atomic spreading and cache-gather / LDS-tile
+    interpolation realise the same operator (each checked against the oracle)."""
+    prob = inputs.random_small(d, 700 if d < 3 else 400, seed=60 + d, nu=1.5, lmin=0.08, lmax=0.2)
+    tol = 1e-9 if prec == 0 else 1e-4
+    bar = FP64_TOL if prec == 0 else FP32_TOL
+    outs = []
+    for sp in (0, 1):
+        for ip in (0, 1):
+            P, info, a, got, ref = _check_matvec(gp, prob, tol=tol, precision=prec, bar=bar, M=M,
+                                                 spread=sp, interp=ip)
+            assert info["spread"] == sp and info["interp"] == ip
+            outs.append(got)
+    for o in outs[1:]:
+        assert rel(o, outs[0]) < (1e-12 if prec == 0 else 1e-5)
+
+
 @pytest.mark.parametrize("d,n,M", [(1, 300, 150), (2, 600, 24), (3, 300, 8)])
 def test_matvec_fp32_vs_oracle(gp, d, n, M):
     prob = inputs.random_small(d, n, seed=3 + d, nu=1.5, lmin=0.08, lmax=0.2)
