@@ -192,6 +192,57 @@ typedef struct {
 int gp_plan_set_timing(gp_plan_t plan, int enable);
 int gp_plan_get_timing(gp_plan_t plan, gp_timing* out);
 
+/* ------------------------------------------------------------- serving -----
+ * Continuous batching of many independent GPR solves (each request: its own
+ * points, scales, nu, eta and y).  The server runs max_slots worker threads,
+ * each with its own HIP stream.  Requests are admitted in arrival order as
+ * soon as a slot is free and the device bytes of the request's plans fit in
+ * max_device_bytes next to the requests in flight; their solves overlap on the
+ * device.  With precision GP_FP32_BULK a request is solved by fp32-bulk CG
+ * inside fp64 iterative refinement (two plans, as gp_cg_solve_refined); with
+ * GP_FP64 by plain fp64 CG.  The caller's device buffers (pts, sigma, l, y,
+ * alpha) must stay valid until the request completes; alpha receives the
+ * solution in the caller's point order. */
+typedef struct gp_server_s* gp_server_t;
+typedef struct {
+  int max_slots;            /* requests in flight at once (1..64) */
+  size_t max_device_bytes;  /* admission budget for the plans of the requests in flight */
+  int precision;            /* GP_FP32_BULK (default) or GP_FP64 */
+  double plan_tol;          /* tolerance of the fp64 operator (default 1e-8) */
+  double plan_tol_bulk;     /* tolerance of the fp32-bulk operator (default 1e-4) */
+  double cg_tol;            /* relative residual target (default 1e-6) */
+  double inner_tol;         /* inner fp32 CG tolerance per refinement pass (default 3e-3) */
+  int max_iter;             /* CG iterations per request, all passes (default 20000) */
+  int max_refine;           /* refinement passes (default 10) */
+} gp_server_opts;
+typedef struct {
+  int status;               /* GP_OK, GP_ENOCONV or an error code */
+  int iters, refinements;
+  double rel_res;           /* final relative residual (fp64 operator) */
+  double t_submit, t_start, t_done;  /* seconds since the server was created */
+  size_t device_bytes;      /* admission bytes of the request */
+  int slot;                 /* worker slot that ran it */
+} gp_request_info;
+typedef struct {
+  int64_t submitted, completed, queued;
+  int running, peak_running;
+  size_t bytes_in_use, peak_bytes;
+  double seconds;           /* since creation */
+} gp_server_counters;
+int gp_server_opts_init(gp_server_opts* opts);
+int gp_server_create(const gp_server_opts* opts, gp_server_t* out);
+/* Queue one solve; returns immediately with its id.  Validates the inputs and
+ * sizes the request (GP_ENOMEM if it can never fit the budget). */
+int gp_server_submit(gp_server_t srv, int d, int64_t n, const double* pts, const double* sigma,
+                     const double* l, double nu, double eta, const double* y, double* alpha,
+                     int64_t* id);
+/* Block until request id has finished; returns its status. */
+int gp_server_wait(gp_server_t srv, int64_t id, gp_request_info* info);
+int gp_server_poll(gp_server_t srv, int64_t id, int* done);
+int gp_server_stats(gp_server_t srv, gp_server_counters* out);
+/* Finish every queued request, then stop the workers and free the server. */
+int gp_server_destroy(gp_server_t srv);
+
 /* Change the stream later work of this plan is ordered on. */
 int gp_plan_set_stream(gp_plan_t plan, void* stream);
 

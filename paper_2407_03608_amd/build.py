@@ -23,6 +23,7 @@ SOURCES = [
     ("gp_mode.hip", "gp_mode32.o", ["-DGP_MODE_FP64=0"]),
     ("gp_cg.hip", "gp_cg.o", []),
     ("gp_capi.hip", "gp_capi.o", []),
+    ("gp_serve.hip", "gp_serve.o", []),
 ]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("GP_OFFLOAD_ARCH", "gfx950")

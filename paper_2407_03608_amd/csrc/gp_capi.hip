@@ -69,6 +69,66 @@ Plan::~Plan() {
   }
   for (auto e : pool) (void)hipEventDestroy(e);
 }
+
+// Iterative refinement in the caller's point order (the two plans may sort the
+// points differently): r = y - A_outer x; A_inner d = r by CG to
+// max(tol ||y||/||r||, inner_tol); x += d; until ||r||/||y|| <= tol.
+int cg_refined_user(Plan* Pi, Plan* Po, const double* y, double* alpha, double tol,
+                    double inner_tol, int max_iter, int max_refine, int replace_every,
+                    int* iters_out, double* rel_out, int* passes_out) {
+  if (Pi->n != Po->n || Pi->d != Po->d) throw Error{GP_EINVAL, "plans differ in n or d"};
+  if (Pi->stream != Po->stream) throw Error{GP_EINVAL, "plans must share a stream"};
+  const int64_t n = Po->n;
+  hipStream_t s = Po->stream;
+  DevBuf rb, db, tb;
+  rb.alloc(n * sizeof(double));
+  db.alloc(n * sizeof(double));
+  tb.alloc(n * sizeof(double));
+  double* r = rb.as<double>();  // user order
+  double* dl = db.as<double>();
+  double* tmp = tb.as<double>();
+  double* Vo = Po->vec.as<double>();
+  double* Vi = Pi->vec.as<double>();
+  GP_HIP(hipMemsetAsync(alpha, 0, n * sizeof(double), s));
+  gather_sorted(Po, y, Vo + 6 * n);
+  const double bb = dot_sorted(Po, Vo + 6 * n, Vo + 6 * n, n);
+  int total = 0, passes = 0;
+  double rel = 1.0, inner_rel = 0;
+  int progress = 0;
+  if (const char* e = std::getenv("GPNUFFT_PROGRESS")) progress = std::atoi(e);
+  while (true) {
+    gather_sorted(Po, alpha, Vo);
+    matvec_sorted(Po, Vo, Vo + n, 1);
+    scatter_user(Po, Vo + n, tmp);
+    hipLaunchKernelGGL(sub_kernel, dim3(blocks(n)), dim3(256), 0, s, n, y, tmp, r);
+    GP_CHECK_LAUNCH();
+    gather_sorted(Po, r, Vo + 7 * n);
+    const double rr = dot_sorted(Po, Vo + 7 * n, Vo + 7 * n, n);
+    rel = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+    if (progress > 0) {
+      std::fprintf(stderr, "[gpnufft] refine pass=%d inner_iters=%d outer_rel_res=%.3e\n", passes,
+                   total, rel);
+      std::fflush(stderr);
+    }
+    if (rel <= tol || passes >= max_refine || total >= max_iter) break;
+    const double itol = std::max(tol / std::max(rel, 1e-300), inner_tol);
+    gather_sorted(Pi, r, Vi + 6 * n);
+    GP_HIP(hipMemsetAsync(Vi + 2 * n, 0, n * sizeof(double), s));
+    int it = 0;
+    (void)cg_solve_sorted(Pi, Vi + 6 * n, Vi + 2 * n, true, itol, max_iter - total, replace_every,
+                          &it, &inner_rel);
+    total += it;
+    scatter_user(Pi, Vi + 2 * n, dl);
+    hipLaunchKernelGGL(axpy_kernel, dim3(blocks(n)), dim3(256), 0, s, n, 1.0, dl, alpha);
+    GP_CHECK_LAUNCH();
+    ++passes;
+  }
+  GP_HIP(hipStreamSynchronize(s));
+  *iters_out = total;
+  *rel_out = rel;
+  *passes_out = passes;
+  return rel <= tol ? GP_OK : GP_ENOCONV;
+}
 }  // namespace gp
 
 using namespace gp;
@@ -223,64 +283,13 @@ int gp_cg_solve_refined(gp_plan_t hin, gp_plan_t hout, const double* y, double* 
                         gp_cg_info* info) {
   return guarded([&] {
     if (!hin || !hout || !y || !alpha) throw Error{GP_EINVAL, "null argument"};
-    Plan* Pi = &hin->P;
-    Plan* Po = &hout->P;
-    if (Pi->n != Po->n || Pi->d != Po->d) throw Error{GP_EINVAL, "plans differ in n or d"};
-    if (Pi->stream != Po->stream) throw Error{GP_EINVAL, "plans must share a stream"};
     auto t0 = std::chrono::steady_clock::now();
-    const int64_t n = Po->n;
-    hipStream_t s = Po->stream;
-    DevBuf rb, db, tb;
-    rb.alloc(n * sizeof(double));
-    db.alloc(n * sizeof(double));
-    tb.alloc(n * sizeof(double));
-    double* r = rb.as<double>();   // user order
-    double* dl = db.as<double>();
-    double* tmp = tb.as<double>();
-    double* Vo = Po->vec.as<double>();
-    double* Vi = Pi->vec.as<double>();
-    GP_HIP(hipMemsetAsync(alpha, 0, n * sizeof(double), s));
-    // bb
-    gather_sorted(Po, y, Vo + 6 * n);
-    const double bb = dot_sorted(Po, Vo + 6 * n, Vo + 6 * n, n);
-    int total = 0, passes = 0, st = GP_OK;
-    double rel = 1.0, inner_rel = 0;
-    while (true) {
-      // r = y - A_outer alpha  (fp64 operator)
-      gather_sorted(Po, alpha, Vo);
-      matvec_sorted(Po, Vo, Vo + n, 1);
-      scatter_user(Po, Vo + n, tmp);
-      hipLaunchKernelGGL(sub_kernel, dim3(blocks(n)), dim3(256), 0, s, n, y, tmp, r);
-      GP_CHECK_LAUNCH();
-      gather_sorted(Po, r, Vo + 7 * n);
-      const double rr = dot_sorted(Po, Vo + 7 * n, Vo + 7 * n, n);
-      rel = bb > 0 ? std::sqrt(rr / bb) : 0.0;
-      if (const char* e = std::getenv("GPNUFFT_PROGRESS")) {
-        if (std::atoi(e) > 0) {
-          std::fprintf(stderr, "[gpnufft] refine pass=%d inner_iters=%d outer_rel_res=%.3e\n", passes,
-                       total, rel);
-          std::fflush(stderr);
-        }
-      }
-      if (rel <= tol || passes >= max_refine || total >= max_iter) break;
-      // inner solve A_inner d = r
-      const double itol = std::max(tol / std::max(rel, 1e-300), inner_tol);
-      gather_sorted(Pi, r, Vi + 6 * n);
-      GP_HIP(hipMemsetAsync(Vi + 2 * n, 0, n * sizeof(double), s));
-      int it = 0;
-      int sti = cg_solve_sorted(Pi, Vi + 6 * n, Vi + 2 * n, true, itol, max_iter - total, replace_every,
-                                &it, &inner_rel);
-      (void)sti;
-      total += it;
-      scatter_user(Pi, Vi + 2 * n, dl);
-      hipLaunchKernelGGL(axpy_kernel, dim3(blocks(n)), dim3(256), 0, s, n, 1.0, dl, alpha);
-      GP_CHECK_LAUNCH();
-      ++passes;
-    }
-    GP_HIP(hipStreamSynchronize(s));
-    st = rel <= tol ? GP_OK : GP_ENOCONV;
+    int iters = 0, passes = 0;
+    double rel = 0;
+    const int st = cg_refined_user(&hin->P, &hout->P, y, alpha, tol, inner_tol, max_iter,
+                                   max_refine, replace_every, &iters, &rel, &passes);
     if (info) {
-      info->iters = total;
+      info->iters = iters;
       info->status = st;
       info->rel_res = rel;
       info->rel_res_true = rel;

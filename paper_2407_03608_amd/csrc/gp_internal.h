@@ -189,6 +189,10 @@ void scatter_user(Plan* P, const double* x_sorted, double* x_user);
 int cg_solve_sorted(Plan* P, const double* b, double* x, bool x_zero, double tol, int max_iter,
                     int replace_every, int* iters, double* rel_res);
 double dot_sorted(Plan* P, const double* a, const double* b, int64_t n);
+// refinement with two plans on the same points, vectors in caller order (capi.hip)
+int cg_refined_user(Plan* Pi, Plan* Po, const double* y, double* alpha, double tol,
+                    double inner_tol, int max_iter, int max_refine, int replace_every,
+                    int* iters, double* rel, int* passes);
 // ||b - (K~ + eta^2 I) x||^2 and ||b||^2 (sorted order)
 void residual_norms(Plan* P, const double* b, const double* x, double* rr, double* bb);
 

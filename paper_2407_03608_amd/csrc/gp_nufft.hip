@@ -19,6 +19,7 @@
 // neighbouring bins), accumulates in LDS with LDS atomics and writes its tile
 // with plain coalesced stores.  No global atomics and no zero-fill pass.
 #include <cmath>
+#include <mutex>
 
 #include "gp_internal.h"
 
@@ -44,6 +45,7 @@ template <> struct V2<float> { using type = float2; };
 constexpr int kThreads = 256;
 constexpr int kPB = 64;      // points staged per batch
 constexpr int kGC = 8;       // max complex grids per chunk
+constexpr int kRG = 4;       // interpolation row groups per (point, grid pair)
 
 struct NuArgs {
   int64_t n;
@@ -362,12 +364,16 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(
   const int pc0 = a.tile[0] + w - 1;
   const int pc1 = D > 1 ? a.tile[1] + w - 1 : 1;
   const int pc2 = D > 2 ? a.tile[2] + w - 1 : 1;
-  const int pcells = pc0 * pc1 * pc2;
+  // tile rows padded to an odd number of cells: the RG lanes of one item group
+  // read RG consecutive rows, which then fall in different LDS banks
+  const int ps0 = pc0 | 1;
+  const int pcells = ps0 * pc1 * pc2;
   const int ls = lds_stride(rs);
   V* tileA = reinterpret_cast<V*>(smem);                                  // [gc][pcells]
   T* s_rec = reinterpret_cast<T*>(tileA + (size_t)a.gc * pcells);         // [kPB][ls]
-  double* s_acc = reinterpret_cast<double*>(s_rec + kPB * ls);            // [kPB] (8-B aligned: kPB*ls*sizeof(T) is a multiple of 256)
-  int* s_cell = reinterpret_cast<int*>(s_acc + kPB);                      // [kPB][D]
+  // per-(point, grid pair) partial sums, reduced in a fixed order
+  double* s_part = reinterpret_cast<double*>(s_rec + kPB * ls);  // [kPB][kGC] (8-B aligned)
+  int* s_cell = reinterpret_cast<int*>(s_part + kPB * kGC);      // [kPB][D]
 
   const int64_t bin = blockIdx.x;
   const int p0 = bin_start[bin], p1 = bin_start[bin + 1];
@@ -380,9 +386,10 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(
       tb /= a.nbins[r];
     }
   }
-  for (int e = threadIdx.x; e < a.gc * pcells; e += kThreads) {
-    const int g = e / pcells;
-    int c = e - g * pcells;
+  const int ucells = pc0 * pc1 * pc2;
+  for (int e = threadIdx.x; e < a.gc * ucells; e += kThreads) {
+    const int g = e / ucells;
+    int c = e - g * ucells;
     const int l0 = c % pc0;
     c /= pc0;
     const int l1 = c % pc1;
@@ -392,11 +399,13 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(
     if (c0 < a.na[0] && (D < 2 || c1 < a.na[1]) && (D < 3 || c2 < a.na[2]))
       v = grid[(int64_t)(a.g0 + g) * a.pair_stride + a.grid_off + (int64_t)c0 * a.gstride[0] +
                (int64_t)c1 * a.gstride[1] + (int64_t)c2 * a.gstride[2]];
-    tileA[e] = v;
+    tileA[(size_t)g * pcells + (l2 * pc1 + l1) * ps0 + l0] = v;
   }
   const int wko = D * w + 2 * a.g0;
   int cellsw = 1;
   for (int r = 1; r < D; ++r) cellsw *= w;
+  // row groups per item: a power of two, so that a group is RG adjacent lanes
+  const int RG = cellsw >= kRG ? kRG : (cellsw >= 2 ? 2 : 1);
   for (int pb = p0; pb < p1; pb += kPB) {
     const int np = min(kPB, p1 - pb);
     __syncthreads();
@@ -404,49 +413,57 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(
       const int p = e / rs;
       s_rec[p * ls + (e - p * rs)] = pw[(int64_t)pb * rs + e];
     }
-    if (threadIdx.x < np) {
+    if (threadIdx.x < np)
       for (int r = 0; r < D; ++r) s_cell[threadIdx.x * D + r] = cell[r * a.n + pb + threadIdx.x] - t0[r];
-      s_acc[threadIdx.x] = 0.0;
-    }
     __syncthreads();
-    // items: (point, window row, grid pair); each adds its row's share of
-    // w_2g beta_2g + w_2g+1 beta_2g+1 to the point's accumulator
-    const int nitems = np * cellsw * a.gc;
+    // items: (row group, point, grid pair) with the row group fastest; a row
+    // group takes window rows rg, rg + RG, ... and the RG lanes of an item
+    // combine their shares of w_2g beta_2g + w_2g+1 beta_2g+1 by xor shuffles
+    // (kThreads and nitems are multiples of RG, so a group is all active or
+    // all inactive)
+    const int nitems = np * a.gc * RG;
     for (int it = threadIdx.x; it < nitems; it += kThreads) {
-      const int p = it % np;
-      const int rest = it / np;
-      const int row = rest % cellsw;
-      const int g = rest / cellsw;
+      const int rg = it % RG;
+      const int rest = it / RG;
+      const int p = rest % np;
+      const int g = rest / np;
       const T* pr = s_rec + p * ls;
-      T wv = T(1);
-      int off = s_cell[p * D];
-      if (D > 1) {
-        const int q1 = row % w;
-        wv *= pr[w + q1];
-        off += (s_cell[p * D + 1] + q1) * pc0;
+      double part = 0.0;
+      for (int row = rg; row < cellsw; row += RG) {
+        T wv = T(1);
+        int off = s_cell[p * D];
+        if (D > 1) {
+          const int q1 = row % w;
+          wv *= pr[w + q1];
+          off += (s_cell[p * D + 1] + q1) * ps0;
+        }
+        if (D > 2) {
+          const int q2 = row / w;
+          wv *= pr[2 * w + q2];
+          off += (s_cell[p * D + 2] + q2) * ps0 * pc1;
+        }
+        const V* tr = tileA + (size_t)g * pcells + off;
+        T rx = 0, ry = 0;
+        for (int q0 = 0; q0 < w; ++q0) {
+          const T ps = pr[q0];
+          const V gv = tr[q0];
+          rx += ps * gv.x;
+          ry += ps * gv.y;
+        }
+        part += (double)wv * ((double)pr[wko + 2 * g] * (double)rx + (double)pr[wko + 2 * g + 1] * (double)ry);
       }
-      if (D > 2) {
-        const int q2 = row / w;
-        wv *= pr[2 * w + q2];
-        off += (s_cell[p * D + 2] + q2) * pc0 * pc1;
-      }
-      const V* tr = tileA + (size_t)g * pcells + off;
-      T rx = 0, ry = 0;
-      for (int q0 = 0; q0 < w; ++q0) {
-        const T ps = pr[q0];
-        const V gv = tr[q0];
-        rx += ps * gv.x;
-        ry += ps * gv.y;
-      }
-      const double contrib =
-          (double)wv * ((double)pr[wko + 2 * g] * (double)rx + (double)pr[wko + 2 * g + 1] * (double)ry);
-      atomicAdd(&s_acc[p], contrib);
+      if (RG >= 2) part += __shfl_xor(part, 1);
+      if (RG >= 4) part += __shfl_xor(part, 2);
+      if (rg == 0) s_part[p * kGC + g] = part;
     }
     __syncthreads();
     if (threadIdx.x < np) {
-      const int64_t i = pb + threadIdx.x;
+      const int p = threadIdx.x;
+      double sum = 0.0;
+      for (int g = 0; g < a.gc; ++g) sum += s_part[p * kGC + g];
+      const int64_t i = pb + p;
       const double base = a.first_chunk ? (a.add_noise ? a.eta2 * x[i] : 0.0) : y[i];
-      y[i] = base + s_acc[threadIdx.x];
+      y[i] = base + sum;
     }
   }
 }
@@ -471,10 +488,10 @@ size_t spread_smem(const Plan* P, int gc, int rs) {
 }
 template <typename T>
 size_t interp_smem(const Plan* P, int gc, int rs) {
-  size_t pc = 1;
-  for (int r = 0; r < P->d; ++r) pc *= (size_t)(P->tile[r] + P->w - 1);
+  size_t pc = (size_t)((P->tile[0] + P->w - 1) | 1);
+  for (int r = 1; r < P->d; ++r) pc *= (size_t)(P->tile[r] + P->w - 1);
   return gc * pc * sizeof(typename V2<T>::type) + (kPB * lds_stride(rs) + 1) * sizeof(T) +
-         kPB * sizeof(double) + kPB * P->d * sizeof(int) + 16;
+         kPB * kGC * sizeof(double) + kPB * P->d * sizeof(int) + 16;
 }
 
 constexpr size_t kSmemCap = 64 * 1024;
@@ -557,12 +574,11 @@ void launch_spread(Plan* P, const double* xs) {
 constexpr size_t kSmemBig = 150 * 1024;
 template <typename K>
 void allow_big_lds(K kernel) {
-  static bool done = false;
-  if (!done) {
-    GP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmemBig));
-    done = true;
-  }
+  static std::once_flag once;
+  std::call_once(once, [&] {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmemBig);
+  });
 }
 
 template <typename T, int D>

@@ -189,8 +189,7 @@ struct RecArgs {
 // sigma_p = l'/sqrt(2), prefactor s(x) (2/(pi l'^2))^(d/4) of eq:Wk.
 __global__ void records_kernel(RecArgs a, const double* __restrict__ pts,
                                const double* __restrict__ sig, const double* __restrict__ l,
-                               int* __restrict__ bin_of, int* __restrict__ rank,
-                               int* __restrict__ counts, int* __restrict__ cell_tmp,
+                               int* __restrict__ bin_of, int* __restrict__ cell_tmp,
                                double* __restrict__ frac_tmp, double* __restrict__ sp_tmp,
                                double* __restrict__ pf_tmp, int* __restrict__ bad) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -214,7 +213,6 @@ __global__ void records_kernel(RecArgs a, const double* __restrict__ pts,
   sp_tmp[i] = lp * 0.70710678118654752440;
   pf_tmp[i] = sig[i] * pow(2.0 / (3.14159265358979323846 * lp * lp), 0.25 * a.d);
   bin_of[i] = (int)bin;
-  rank[i] = atomicAdd(&counts[bin], 1);
 }
 
 // Scatter the per-point data into bin order and evaluate, once per plan, the
@@ -223,9 +221,7 @@ __global__ void records_kernel(RecArgs a, const double* __restrict__ pts,
 // Lagrange basis in barycentric form on the Chebyshev-Lobatto nodes.
 template <typename T>
 __global__ void scatter_records_kernel(int d, int64_t n, int w, double beta, int nk, int nkp,
-                                       int rs, const int* __restrict__ bin_of,
-                                       const int* __restrict__ rank,
-                                       const int* __restrict__ bin_start,
+                                       int rs, const int* __restrict__ posv,
                                        const int* __restrict__ cell_tmp,
                                        const double* __restrict__ frac_tmp,
                                        const double* __restrict__ sp_tmp,
@@ -235,7 +231,7 @@ __global__ void scatter_records_kernel(int d, int64_t n, int w, double beta, int
                                        int* __restrict__ cell, T* __restrict__ pw) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int64_t pos = (int64_t)bin_start[bin_of[i]] + rank[i];
+  const int64_t pos = posv[i];
   perm[pos] = (int)i;
   T* row = pw + pos * rs;
   const double tw = 2.0 / w;
@@ -319,37 +315,34 @@ void build_records_into(Plan* P, int64_t n, const double* pts, const double* sig
   a.dw = P->dw;
   a.w = P->w;
   const size_t tsz = P->precision == GP_FP64 ? sizeof(double) : sizeof(float);
-  DevBuf bin_of, rank, counts, cell_tmp, frac_tmp, sp_tmp, pf_tmp, bad;
+  DevBuf bin_of, posd, cell_tmp, frac_tmp, sp_tmp, pf_tmp, bad;
   bin_of.alloc(n * sizeof(int));
-  rank.alloc(n * sizeof(int));
-  counts.alloc((P->n_bins + 1) * sizeof(int));
+  posd.alloc(n * sizeof(int));
   cell_tmp.alloc(n * d * sizeof(int));
   frac_tmp.alloc(n * d * sizeof(double));
   sp_tmp.alloc(n * sizeof(double));
   pf_tmp.alloc(n * sizeof(double));
   bad.alloc(sizeof(int));
-  GP_HIP(hipMemsetAsync(counts.p, 0, (P->n_bins + 1) * sizeof(int), s));
   GP_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
   const int bs = 256;
   const unsigned nb = (unsigned)((n + bs - 1) / bs);
   hipLaunchKernelGGL(records_kernel, dim3(nb), dim3(bs), 0, s, a, pts, sig, l, bin_of.as<int>(),
-                     rank.as<int>(), counts.as<int>(), cell_tmp.as<int>(),
-                     frac_tmp.as<double>(), sp_tmp.as<double>(), pf_tmp.as<double>(),
-                     bad.as<int>());
+                     cell_tmp.as<int>(), frac_tmp.as<double>(), sp_tmp.as<double>(),
+                     pf_tmp.as<double>(), bad.as<int>());
   GP_CHECK_LAUNCH();
-  std::vector<int> hc(P->n_bins + 1);
+  // Stable counting sort by tile on the host (plan time): points keep their
+  // caller order inside a tile, so every plan of the same input is identical.
+  std::vector<int> hb(n);
   int hbad = 0;
-  GP_HIP(hipMemcpyAsync(hc.data(), counts.p, P->n_bins * sizeof(int), hipMemcpyDeviceToHost, s));
+  GP_HIP(hipMemcpyAsync(hb.data(), bin_of.p, n * sizeof(int), hipMemcpyDeviceToHost, s));
   GP_HIP(hipMemcpyAsync(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
   GP_HIP(hipStreamSynchronize(s));
   if (out_of_box) *out_of_box = hbad;
-  std::vector<int> start(P->n_bins + 1);
-  int64_t acc = 0;
-  for (int64_t b = 0; b < P->n_bins; ++b) {
-    start[b] = (int)acc;
-    acc += hc[b];
-  }
-  start[P->n_bins] = (int)acc;
+  std::vector<int> start(P->n_bins + 1, 0);
+  for (int64_t i = 0; i < n; ++i) start[hb[i] + 1] += 1;
+  for (int64_t b = 0; b < P->n_bins; ++b) start[b + 1] += start[b];
+  std::vector<int> fill(start.begin(), start.end() - 1), hpos(n);
+  for (int64_t i = 0; i < n; ++i) hpos[i] = fill[hb[i]]++;
   R.n = n;
   R.rs = d * P->w + P->nkp;
   R.perm.alloc(n * sizeof(int));
@@ -358,10 +351,11 @@ void build_records_into(Plan* P, int64_t n, const double* pts, const double* sig
   R.bin_start.alloc((P->n_bins + 1) * sizeof(int));
   GP_HIP(hipMemcpyAsync(R.bin_start.p, start.data(), (P->n_bins + 1) * sizeof(int),
                         hipMemcpyHostToDevice, s));
+  GP_HIP(hipMemcpyAsync(posd.p, hpos.data(), n * sizeof(int), hipMemcpyHostToDevice, s));
 #define GP_SCATTER(T)                                                                            \
   hipLaunchKernelGGL(scatter_records_kernel<T>, dim3(nb), dim3(bs), 0, s, d, n, P->w, P->beta, \
-                     P->nk, P->nkp, R.rs, bin_of.as<int>(), rank.as<int>(),                    \
-                     R.bin_start.as<int>(), cell_tmp.as<int>(), frac_tmp.as<double>(),         \
+                     P->nk, P->nkp, R.rs, posd.as<int>(), cell_tmp.as<int>(),                  \
+                     frac_tmp.as<double>(),                                                    \
                      sp_tmp.as<double>(), pf_tmp.as<double>(), P->nodes_d.as<double>(),        \
                      P->bary_d.as<double>(), R.perm.as<int>(), R.cell.as<int>(), R.pw.as<T>())
   if (P->precision == GP_FP64)

@@ -1,0 +1,341 @@
+// Continuous-batching request loop for many independent GPR solves.
+//
+// Each request is one solve of (K~ + eta^2 I) alpha = y (eq:gprsolve) on its own
+// points and hyperparameters.  The server owns `max_slots` worker threads,
+// each with its own non-blocking HIP stream.  A request is admitted in arrival
+// order as soon as a slot is free and the device bytes of its plans fit in the
+// budget next to the requests already in flight; its plan(s) are built, the
+// solve runs on the slot's stream (so requests overlap on the device), alpha
+// is written to the caller's buffer and the plans are released.
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+
+#include "gp_internal.h"
+
+namespace gp {
+
+struct SRequest {
+  int64_t id = 0;
+  int d = 0;
+  int64_t n = 0;
+  const double *pts = nullptr, *sigma = nullptr, *l = nullptr, *y = nullptr;
+  double* alpha = nullptr;
+  double nu = 0, eta = 0;
+  size_t bytes = 0;
+  double t_submit = 0, t_start = -1, t_done = -1;
+  int status = GP_OK, iters = 0, refinements = 0, slot = -1;
+  double rel_res = 0;
+  bool done = false;
+  std::string err;
+};
+
+struct Server {
+  gp_server_opts o;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<SRequest*> queue;
+  std::map<int64_t, std::unique_ptr<SRequest>> all;
+  size_t bytes_in_use = 0, peak_bytes = 0;
+  int running = 0, peak_running = 0;
+  int64_t next_id = 1, completed = 0;
+  bool stop = false;
+  std::vector<std::thread> workers;
+  std::vector<hipStream_t> streams;
+  hipStream_t qstream = nullptr;  // for admission queries
+  std::chrono::steady_clock::time_point t0;
+  double now() const {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+};
+
+namespace {
+
+void fill_opts(const Server& S, int bulk, hipStream_t st, gp_opts* o) {
+  gp_opts_init(o);
+  o->precision = bulk ? GP_FP32_BULK : GP_FP64;
+  o->stream = st;
+}
+
+// Device bytes the request's plan(s) will hold.
+size_t request_bytes(Server& S, const SRequest& r) {
+  gp_opts o;
+  size_t b64 = 0, b32 = 0;
+  fill_opts(S, 0, S.qstream, &o);
+  Plan q64;
+  build_plan(r.d, r.n, r.pts, r.sigma, r.l, r.nu, r.eta, S.o.plan_tol, &o, &q64, true, &b64);
+  if (S.o.precision == GP_FP64) return b64;
+  fill_opts(S, 1, S.qstream, &o);
+  o.dw = q64.dw;
+  o.M = q64.M;
+  Plan q32;
+  build_plan(r.d, r.n, r.pts, r.sigma, r.l, r.nu, r.eta, S.o.plan_tol_bulk, &o, &q32, true, &b32);
+  return b64 + b32;
+}
+
+void run_request(Server& S, SRequest& r, hipStream_t st) {
+  gp_opts o;
+  fill_opts(S, 0, st, &o);
+  Plan P64;
+  build_plan(r.d, r.n, r.pts, r.sigma, r.l, r.nu, r.eta, S.o.plan_tol, &o, &P64, false, nullptr);
+  if (S.o.precision == GP_FP64) {
+    double* V = P64.vec.as<double>();
+    gather_sorted(&P64, r.y, V + 6 * r.n);
+    GP_HIP(hipMemsetAsync(V + 2 * r.n, 0, r.n * sizeof(double), st));
+    int it = 0;
+    double rel = 0;
+    r.status = cg_solve_sorted(&P64, V + 6 * r.n, V + 2 * r.n, true, S.o.cg_tol, S.o.max_iter, 0,
+                               &it, &rel);
+    scatter_user(&P64, V + 2 * r.n, r.alpha);
+    GP_HIP(hipStreamSynchronize(st));
+    r.iters = it;
+    r.rel_res = rel;
+    return;
+  }
+  fill_opts(S, 1, st, &o);
+  o.dw = P64.dw;
+  o.M = P64.M;
+  Plan P32;
+  build_plan(r.d, r.n, r.pts, r.sigma, r.l, r.nu, r.eta, S.o.plan_tol_bulk, &o, &P32, false, nullptr);
+  int it = 0, passes = 0;
+  double rel = 0;
+  r.status = cg_refined_user(&P32, &P64, r.y, r.alpha, S.o.cg_tol, S.o.inner_tol, S.o.max_iter,
+                             S.o.max_refine, 0, &it, &rel, &passes);
+  r.iters = it;
+  r.rel_res = rel;
+  r.refinements = passes;
+}
+
+void worker(Server* S, int slot) {
+  hipStream_t st = S->streams[slot];
+  while (true) {
+    SRequest* r = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv_work.wait(lk, [&] {
+        if (S->stop && S->queue.empty()) return true;
+        if (S->queue.empty()) return false;
+        return S->bytes_in_use + S->queue.front()->bytes <= S->o.max_device_bytes ||
+               S->running == 0;
+      });
+      if (S->queue.empty()) return;  // stop requested and nothing left
+      r = S->queue.front();
+      S->queue.pop_front();
+      S->bytes_in_use += r->bytes;
+      S->peak_bytes = std::max(S->peak_bytes, S->bytes_in_use);
+      S->running += 1;
+      S->peak_running = std::max(S->peak_running, S->running);
+      r->t_start = S->now();
+      r->slot = slot;
+    }
+    try {
+      run_request(*S, *r, st);
+    } catch (const Error& e) {
+      r->status = e.code;
+      r->err = e.msg;
+    } catch (const std::exception& e) {
+      r->status = GP_EDEVICE;
+      r->err = e.what();
+    }
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->bytes_in_use -= r->bytes;
+      S->running -= 1;
+      S->completed += 1;
+      r->t_done = S->now();
+      r->done = true;
+    }
+    S->cv_done.notify_all();
+    S->cv_work.notify_all();
+  }
+}
+
+}  // namespace
+}  // namespace gp
+
+using namespace gp;
+
+struct gp_server_s {
+  Server S;
+};
+
+template <class F>
+static int sguard(F&& f) {
+  try {
+    clear_error();
+    return f();
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return GP_EDEVICE;
+  }
+}
+
+extern "C" {
+
+int gp_server_opts_init(gp_server_opts* o) {
+  if (!o) return GP_EINVAL;
+  std::memset(o, 0, sizeof(*o));
+  o->max_slots = 4;
+  o->max_device_bytes = (size_t)64 << 30;
+  o->precision = GP_FP32_BULK;
+  o->plan_tol = 1e-8;
+  o->plan_tol_bulk = 1e-4;
+  o->cg_tol = 1e-6;
+  o->inner_tol = 3e-3;
+  o->max_iter = 20000;
+  o->max_refine = 10;
+  return GP_OK;
+}
+
+int gp_server_create(const gp_server_opts* opts, gp_server_t* out) {
+  return sguard([&] {
+    if (!opts || !out) throw Error{GP_EINVAL, "null argument"};
+    if (opts->max_slots < 1 || opts->max_slots > 64) throw Error{GP_EINVAL, "max_slots in 1..64"};
+    if (opts->precision != GP_FP64 && opts->precision != GP_FP32_BULK)
+      throw Error{GP_EINVAL, "unknown precision"};
+    auto* h = new gp_server_s();
+    Server& S = h->S;
+    S.o = *opts;
+    S.t0 = std::chrono::steady_clock::now();
+    try {
+      GP_HIP(hipStreamCreateWithFlags(&S.qstream, hipStreamNonBlocking));
+      for (int k = 0; k < opts->max_slots; ++k) {
+        hipStream_t st;
+        GP_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        S.streams.push_back(st);
+      }
+      for (int k = 0; k < opts->max_slots; ++k) S.workers.emplace_back(worker, &S, k);
+    } catch (...) {
+      {
+        std::lock_guard<std::mutex> lk(S.mu);
+        S.stop = true;
+      }
+      S.cv_work.notify_all();
+      for (auto& t : S.workers) t.join();
+      for (auto st : S.streams) (void)hipStreamDestroy(st);
+      if (S.qstream) (void)hipStreamDestroy(S.qstream);
+      delete h;
+      throw;
+    }
+    *out = h;
+    return GP_OK;
+  });
+}
+
+int gp_server_submit(gp_server_t h, int d, int64_t n, const double* pts, const double* sigma,
+                     const double* l, double nu, double eta, const double* y, double* alpha,
+                     int64_t* id) {
+  return sguard([&] {
+    if (!h || !pts || !sigma || !l || !y || !alpha || !id) throw Error{GP_EINVAL, "null argument"};
+    Server& S = h->S;
+    auto r = std::make_unique<SRequest>();
+    r->d = d;
+    r->n = n;
+    r->pts = pts;
+    r->sigma = sigma;
+    r->l = l;
+    r->y = y;
+    r->alpha = alpha;
+    r->nu = nu;
+    r->eta = eta;
+    r->t_submit = S.now();
+    r->bytes = request_bytes(S, *r);  // validates the inputs too
+    if (r->bytes > S.o.max_device_bytes)
+      throw Error{GP_ENOMEM, "request needs " + std::to_string(r->bytes) +
+                                 " device bytes, more than the server budget"};
+    SRequest* raw = r.get();
+    {
+      std::lock_guard<std::mutex> lk(S.mu);
+      if (S.stop) throw Error{GP_EINVAL, "server is shutting down"};
+      raw->id = S.next_id++;
+      S.all[raw->id] = std::move(r);
+      S.queue.push_back(raw);
+    }
+    S.cv_work.notify_all();
+    *id = raw->id;
+    return GP_OK;
+  });
+}
+
+static void fill_info(const SRequest& r, gp_request_info* info) {
+  info->status = r.status;
+  info->iters = r.iters;
+  info->refinements = r.refinements;
+  info->rel_res = r.rel_res;
+  info->t_submit = r.t_submit;
+  info->t_start = r.t_start;
+  info->t_done = r.t_done;
+  info->device_bytes = r.bytes;
+  info->slot = r.slot;
+}
+
+int gp_server_wait(gp_server_t h, int64_t id, gp_request_info* info) {
+  return sguard([&] {
+    if (!h) throw Error{GP_EINVAL, "null server"};
+    Server& S = h->S;
+    std::unique_lock<std::mutex> lk(S.mu);
+    auto itr = S.all.find(id);
+    if (itr == S.all.end()) throw Error{GP_EINVAL, "unknown request id"};
+    SRequest* r = itr->second.get();
+    S.cv_done.wait(lk, [&] { return r->done; });
+    if (info) fill_info(*r, info);
+    if (r->status != GP_OK && r->status != GP_ENOCONV) set_error(r->err);
+    return r->status;
+  });
+}
+
+int gp_server_poll(gp_server_t h, int64_t id, int* done) {
+  return sguard([&] {
+    if (!h || !done) throw Error{GP_EINVAL, "null argument"};
+    Server& S = h->S;
+    std::lock_guard<std::mutex> lk(S.mu);
+    auto itr = S.all.find(id);
+    if (itr == S.all.end()) throw Error{GP_EINVAL, "unknown request id"};
+    *done = itr->second->done ? 1 : 0;
+    return GP_OK;
+  });
+}
+
+int gp_server_stats(gp_server_t h, gp_server_counters* st) {
+  return sguard([&] {
+    if (!h || !st) throw Error{GP_EINVAL, "null argument"};
+    Server& S = h->S;
+    std::lock_guard<std::mutex> lk(S.mu);
+    st->submitted = S.next_id - 1;
+    st->completed = S.completed;
+    st->running = S.running;
+    st->queued = (int64_t)S.queue.size();
+    st->peak_running = S.peak_running;
+    st->bytes_in_use = S.bytes_in_use;
+    st->peak_bytes = S.peak_bytes;
+    st->seconds = S.now();
+    return GP_OK;
+  });
+}
+
+int gp_server_destroy(gp_server_t h) {
+  return sguard([&] {
+    if (!h) return GP_OK;
+    Server& S = h->S;
+    {
+      std::lock_guard<std::mutex> lk(S.mu);
+      S.stop = true;
+    }
+    S.cv_work.notify_all();
+    for (auto& t : S.workers) t.join();
+    for (auto st : S.streams) (void)hipStreamDestroy(st);
+    if (S.qstream) (void)hipStreamDestroy(S.qstream);
+    delete h;
+    return GP_OK;
+  });
+}
+
+}  // extern "C"

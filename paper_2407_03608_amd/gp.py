@@ -120,7 +120,55 @@ EXPORTS = [
     "gp_residual",
     "gp_plan_set_timing",
     "gp_plan_get_timing",
+    "gp_server_opts_init",
+    "gp_server_create",
+    "gp_server_submit",
+    "gp_server_wait",
+    "gp_server_poll",
+    "gp_server_stats",
+    "gp_server_destroy",
 ]
+
+
+class GpServerOpts(ctypes.Structure):
+    _fields_ = [
+        ("max_slots", _c_i),
+        ("max_device_bytes", _c_sz),
+        ("precision", _c_i),
+        ("plan_tol", _c_d),
+        ("plan_tol_bulk", _c_d),
+        ("cg_tol", _c_d),
+        ("inner_tol", _c_d),
+        ("max_iter", _c_i),
+        ("max_refine", _c_i),
+    ]
+
+
+class GpRequestInfo(ctypes.Structure):
+    _fields_ = [
+        ("status", _c_i),
+        ("iters", _c_i),
+        ("refinements", _c_i),
+        ("rel_res", _c_d),
+        ("t_submit", _c_d),
+        ("t_start", _c_d),
+        ("t_done", _c_d),
+        ("device_bytes", _c_sz),
+        ("slot", _c_i),
+    ]
+
+
+class GpServerCounters(ctypes.Structure):
+    _fields_ = [
+        ("submitted", _c_i64),
+        ("completed", _c_i64),
+        ("queued", _c_i64),
+        ("running", _c_i),
+        ("peak_running", _c_i),
+        ("bytes_in_use", _c_sz),
+        ("peak_bytes", _c_sz),
+        ("seconds", _c_d),
+    ]
 
 TIMING_PHASES = 10
 
@@ -177,6 +225,21 @@ def load(path: str = LIB_PATH):
     L.gp_plan_set_timing.restype = _c_i
     L.gp_plan_get_timing.argtypes = [_c_p, ctypes.POINTER(GpTiming)]
     L.gp_plan_get_timing.restype = _c_i
+    L.gp_server_opts_init.argtypes = [ctypes.POINTER(GpServerOpts)]
+    L.gp_server_opts_init.restype = _c_i
+    L.gp_server_create.argtypes = [ctypes.POINTER(GpServerOpts), ctypes.POINTER(_c_p)]
+    L.gp_server_create.restype = _c_i
+    L.gp_server_submit.argtypes = [_c_p, _c_i, _c_i64, _c_p, _c_p, _c_p, _c_d, _c_d, _c_p, _c_p,
+                                   ctypes.POINTER(_c_i64)]
+    L.gp_server_submit.restype = _c_i
+    L.gp_server_wait.argtypes = [_c_p, _c_i64, ctypes.POINTER(GpRequestInfo)]
+    L.gp_server_wait.restype = _c_i
+    L.gp_server_poll.argtypes = [_c_p, _c_i64, ctypes.POINTER(_c_i)]
+    L.gp_server_poll.restype = _c_i
+    L.gp_server_stats.argtypes = [_c_p, ctypes.POINTER(GpServerCounters)]
+    L.gp_server_stats.restype = _c_i
+    L.gp_server_destroy.argtypes = [_c_p]
+    L.gp_server_destroy.restype = _c_i
     _lib = L
     return L
 
@@ -343,3 +406,65 @@ def cg_solve_refined(inner: Plan, outer: Plan, y: torch.Tensor, tol: float = 1e-
     if rc not in (GP_OK, GP_ENOCONV):
         _check(rc)
     return alpha, _info_dict(info)
+
+
+class Server:
+    """Continuous-batching solve server (gp_server_*).  Submitted tensors are
+    kept alive here until their request has been waited for."""
+
+    def __init__(self, max_slots: int = 4, max_device_bytes: int = 64 << 30,
+                 precision: int = GP_FP32_BULK, **kw):
+        L = load()
+        o = GpServerOpts()
+        _check(L.gp_server_opts_init(ctypes.byref(o)))
+        o.max_slots = max_slots
+        o.max_device_bytes = max_device_bytes
+        o.precision = precision
+        for k, v in kw.items():
+            setattr(o, k, v)
+        h = _c_p()
+        _check(L.gp_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self._live = {}
+
+    def submit(self, x, sigma, l, nu, eta, y) -> int:
+        x = _dev(x, "x")
+        if x.dim() == 1:
+            x = x[:, None].contiguous()
+        sigma, l, y = _dev(sigma, "sigma"), _dev(l, "l"), _dev(y, "y")
+        alpha = torch.empty_like(y)
+        rid = _c_i64()
+        _check(load().gp_server_submit(self._h, x.shape[1], x.shape[0], x.data_ptr(),
+                                       sigma.data_ptr(), l.data_ptr(), float(nu), float(eta),
+                                       y.data_ptr(), alpha.data_ptr(), ctypes.byref(rid)))
+        self._live[rid.value] = (x, sigma, l, y, alpha)
+        return rid.value
+
+    def wait(self, rid: int):
+        info = GpRequestInfo()
+        rc = load().gp_server_wait(self._h, rid, ctypes.byref(info))
+        if rc not in (GP_OK, GP_ENOCONV):
+            _check(rc)
+        alpha = self._live.pop(rid)[4]
+        return alpha, {name: getattr(info, name) for name, _ in GpRequestInfo._fields_}
+
+    def poll(self, rid: int) -> bool:
+        d = _c_i()
+        _check(load().gp_server_poll(self._h, rid, ctypes.byref(d)))
+        return bool(d.value)
+
+    def stats(self) -> dict:
+        c = GpServerCounters()
+        _check(load().gp_server_stats(self._h, ctypes.byref(c)))
+        return {name: getattr(c, name) for name, _ in GpServerCounters._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().gp_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
