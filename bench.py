@@ -10,6 +10,13 @@ stepped through the fp32-bulk path (fp32 grids, fp64 vectors) and reported
 beside it.  Inputs are synthetic (seeded) and resident in HBM before timing.
 
   python bench.py [--steps K] [--warmup W] [--solve] [--no-cpu]
+  python bench.py --serving [--requests R] [--slots S]
+
+--serving replays a Poisson stream of independent GPR solve requests
+(d in {1,2}, N log-uniform in [1e3, 5e5], random smooth sigma/l, fp32-bulk
+operator with fp64 refinement to 1e-6) against the continuous-batching server
+and reports latency percentiles (arrival to alpha ready), solves/s and the
+admitted concurrency.
 """
 from __future__ import annotations
 
@@ -42,6 +49,12 @@ def parse():
                     help="end with one device copy of this size (HBM counter calibration)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--serving", action="store_true", help="serving benchmark instead of matvec steps")
+    ap.add_argument("--requests", type=int, default=512)
+    ap.add_argument("--rate", type=float, default=50.0)
+    ap.add_argument("--slots", type=int, default=8)
+    ap.add_argument("--serve-bytes-gib", type=float, default=200.0)
+    ap.add_argument("--serve-max-iter", type=int, default=20000)
     return ap.parse_args()
 
 
@@ -138,12 +151,112 @@ def cpu_baseline(prob, seconds):
                       f"({rows * prob.n:.2e} kernel evaluations, {t:.1f} s)"}
 
 
+def serving(args):
+    """Requests are submitted at their arrival times; the server admits them in
+    order as slots and device bytes allow.  Inputs are resident in HBM before
+    the stream starts."""
+    import numpy as np
+    import torch
+
+    from paper_2407_03608_amd import gp, inputs
+
+    assert torch.cuda.is_available()
+    log(f"generating {args.requests} requests")
+    reqs = inputs.serving_stream(n_requests=args.requests, rate=args.rate, seed=5)
+    dev = []
+    for r in reqs:
+        p = r.problem
+        dev.append(tuple(torch.as_tensor(np.ascontiguousarray(v)).to("cuda")
+                         for v in (p.x, p.sigma, p.l, p.y)))
+    torch.cuda.synchronize()
+    S = gp.Server(max_slots=args.slots, max_device_bytes=int(args.serve_bytes_gib * (1 << 30)),
+                  precision=gp.GP_FP32_BULK, max_iter=args.serve_max_iter)
+    # warm-up: one small request end to end (kernel loading, first allocations)
+    w = inputs.random_small(2, 2000, seed=9, nu=1.5, lmin=0.05, lmax=0.1)
+    wid = S.submit(*(torch.as_tensor(v).to("cuda") for v in (w.x, w.sigma, w.l)), w.nu, w.eta,
+                   torch.as_tensor(w.y).to("cuda"))
+    S.wait(wid)
+    log("stream start")
+    ids = []
+    t0 = time.perf_counter()
+    done = 0
+    results = {}
+
+    def drain(block):
+        nonlocal done
+        for rid, k in list(pending.items()):
+            if block or S.poll(rid):
+                _, info = S.wait(rid)
+                results[k] = info
+                del pending[rid]
+                done += 1
+                p = reqs[k].problem
+                log(f"  done {done}/{len(reqs)} req {k} d={p.d} n={p.n} nu={p.nu} "
+                    f"iters={info['iters']} status={info['status']} "
+                    f"latency={info['t_done'] - info['t_submit']:.3f}s")
+
+    pending = {}
+    for k, r in enumerate(reqs):
+        while True:
+            now = time.perf_counter() - t0
+            if now >= r.arrival:
+                break
+            drain(False)
+            time.sleep(min(0.002, r.arrival - now))
+        x, sg, l, y = dev[k]
+        pending[S.submit(x, sg, l, r.problem.nu, r.problem.eta, y)] = k
+    while pending:
+        drain(False)
+        time.sleep(0.005)
+    wall = time.perf_counter() - t0
+    st = S.stats()
+    S.close()
+    lat = np.array([results[k]["t_done"] - results[k]["t_submit"] for k in range(len(reqs))])
+    queue = np.array([results[k]["t_start"] - results[k]["t_submit"] for k in range(len(reqs))])
+    iters = np.array([results[k]["iters"] for k in range(len(reqs))])
+    nonconv = int(sum(results[k]["status"] != 0 for k in range(len(reqs))))
+    out = {
+        "metric": "p99 latency of GPR solve requests (arrival to alpha ready), Poisson stream",
+        "value": round(float(np.percentile(lat, 99)), 4),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": len(reqs),
+        "warmup": 1,
+        "ms_per_step": round(1e3 * wall / len(reqs), 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-bulk/f64",
+        "data": "synthetic (seeded request stream)",
+        "config": {"workload": f"serving: {len(reqs)} requests, Poisson {args.rate}/s, d in {{1,2}}, "
+                               "N log-uniform [1e3,5e5], nu in {1/2,3/2,5/2}, fp32-bulk + fp64 refinement, "
+                               "CG 1e-6", "slots": args.slots, "max_iter": args.serve_max_iter},
+        "serving": {"p50_s": round(float(np.percentile(lat, 50)), 4),
+                    "p90_s": round(float(np.percentile(lat, 90)), 4),
+                    "p99_s": round(float(np.percentile(lat, 99)), 4),
+                    "max_s": round(float(lat.max()), 4),
+                    "mean_queue_s": round(float(queue.mean()), 4),
+                    "solves_per_s": round(len(reqs) / wall, 3),
+                    "wall_s": round(wall, 3),
+                    "peak_running": st["peak_running"],
+                    "peak_bytes": st["peak_bytes"],
+                    "nonconverged": nonconv,
+                    "iters_p50": int(np.percentile(iters, 50)),
+                    "iters_max": int(iters.max()),
+                    "points_total": int(sum(r.problem.n for r in reqs))},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is a "
               "design note, not an implemented path.", file=sys.stderr)
         sys.exit(2)
+    if args.serving:
+        serving(args)
+        return
     import torch
 
     from paper_2407_03608_amd import gp, inputs

@@ -199,8 +199,11 @@ int gp_plan_get_timing(gp_plan_t plan, gp_timing* out);
  * soon as a slot is free and the device bytes of the request's plans fit in
  * max_device_bytes next to the requests in flight; their solves overlap on the
  * device.  With precision GP_FP32_BULK a request is solved by fp32-bulk CG
- * inside fp64 iterative refinement (two plans, as gp_cg_solve_refined); with
- * GP_FP64 by plain fp64 CG.  The caller's device buffers (pts, sigma, l, y,
+ * inside fp64 iterative refinement (two plans, as gp_cg_solve_refined),
+ * unless its fp64 plan needs fewer than fp64_below_bytes of device memory (a
+ * small operator whose matvec is bound by launch latency, where the fp32 grids
+ * save nothing); those, and every request under GP_FP64, are solved by plain
+ * fp64 CG.  The caller's device buffers (pts, sigma, l, y,
  * alpha) must stay valid until the request completes; alpha receives the
  * solution in the caller's point order. */
 typedef struct gp_server_s* gp_server_t;
@@ -214,6 +217,7 @@ typedef struct {
   double inner_tol;         /* inner fp32 CG tolerance per refinement pass (default 3e-3) */
   int max_iter;             /* CG iterations per request, all passes (default 20000) */
   int max_refine;           /* refinement passes (default 10) */
+  size_t fp64_below_bytes;  /* fp64 CG for requests whose fp64 plan is smaller (default 256 MiB) */
 } gp_server_opts;
 typedef struct {
   int status;               /* GP_OK, GP_ENOCONV or an error code */
@@ -222,6 +226,7 @@ typedef struct {
   double t_submit, t_start, t_done;  /* seconds since the server was created */
   size_t device_bytes;      /* admission bytes of the request */
   int slot;                 /* worker slot that ran it */
+  int precision;            /* path it was solved on: GP_FP64 or GP_FP32_BULK */
 } gp_request_info;
 typedef struct {
   int64_t submitted, completed, queued;

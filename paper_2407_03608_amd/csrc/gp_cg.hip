@@ -2,8 +2,12 @@
 // matvec in CG with a relative-residual stopping rule).  Vectors are fp64 and
 // live in the plan's bin-sorted point order; dot products are two-stage
 // reductions with a fixed block count, so they are deterministic.  The step
-// lengths alpha, beta stay on the device; the host reads ||r||^2 once per
-// iteration for the stopping test.
+// lengths alpha, beta and the stopping test stay on the device: the iteration
+// that reaches the tolerance raises a done flag, after which the vector
+// updates of iterations already queued do nothing.  The host queues
+// iterations in batches and reads the flag between batches, so the iterate
+// and the iteration count are those of a loop that tests every iteration.
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -39,8 +43,10 @@ __global__ __launch_bounds__(kRedThreads) void dot_partial(int64_t n, const doub
   if (threadIdx.x == 0) part[blockIdx.x] = v;
 }
 
-// S layout: 0 rr, 1 pAp, 2 rr_new, 3 bb, 4 beta, 5 scratch
-// mode 0: S[slot] = sum; mode 1 (rr update): S[2] = sum, S[4] = sum / S[0], S[0] = sum
+// S layout: 0 rr, 1 pAp, 2 rr_new, 3 bb, 4 beta, 5 scratch, 6 stopping
+// threshold on rr, 7 done flag, 8 completed iterations
+// mode 0: S[slot] = sum; mode 1 (rr update, skipped once done): S[2] = sum,
+// S[4] = sum / S[0], S[0] = sum, one more iteration, done if sum <= S[6]
 __global__ __launch_bounds__(kRedThreads) void dot_final(int nparts, const double* __restrict__ part,
                                                          double* __restrict__ S, int slot, int mode) {
   double v = 0;
@@ -49,11 +55,21 @@ __global__ __launch_bounds__(kRedThreads) void dot_final(int nparts, const doubl
   if (threadIdx.x == 0) {
     if (mode == 0) {
       S[slot] = v;
-    } else {
+    } else if (S[7] == 0.0) {
       S[2] = v;
       S[4] = v / S[0];
       S[0] = v;
+      S[8] += 1.0;
+      if (v <= S[6]) S[7] = 1.0;
     }
+  }
+}
+
+__global__ void cg_init_flags(double* S, double stop2) {
+  if (threadIdx.x == 0) {
+    S[6] = stop2;
+    S[7] = 0.0;
+    S[8] = 0.0;
   }
 }
 
@@ -64,6 +80,7 @@ __global__ __launch_bounds__(kRedThreads) void update_xr(int64_t n, const double
                                                          const double* __restrict__ p,
                                                          const double* __restrict__ Ap,
                                                          double* __restrict__ part) {
+  if (S[7] != 0.0) return;
   const double a = S[0] / S[1];
   double v = 0;
   for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n;
@@ -80,6 +97,7 @@ __global__ __launch_bounds__(kRedThreads) void update_xr(int64_t n, const double
 // p = r + beta p, beta = S[4]
 __global__ void update_p(int64_t n, const double* __restrict__ S, const double* __restrict__ r,
                          double* __restrict__ p) {
+  if (S[7] != 0.0) return;
   const double b = S[4];
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -110,8 +128,8 @@ struct Scratch {
   double* hS = nullptr;
   Scratch() {
     part.alloc(kRedBlocks * sizeof(double));
-    S.alloc(8 * sizeof(double));
-    GP_HIP(hipHostMalloc((void**)&hS, 8 * sizeof(double), hipHostMallocDefault));
+    S.alloc(16 * sizeof(double));
+    GP_HIP(hipHostMalloc((void**)&hS, 16 * sizeof(double), hipHostMallocDefault));
   }
   ~Scratch() {
     if (hS) (void)hipHostFree(hS);
@@ -188,41 +206,67 @@ int cg_solve_sorted(Plan* P, const double* b, double* x, bool x_zero, double tol
   // optional progress lines on stderr every GPNUFFT_PROGRESS iterations
   int progress = 0;
   if (const char* e = std::getenv("GPNUFFT_PROGRESS")) progress = std::atoi(e);
-  int it = 0;
-  while (rr > stop2 && it < max_iter) {
-    ++it;
-    matvec_sorted(P, p, Ap, 1);
-    {
-      PhaseScope ps(P, PH_CG);
-      dot_into(P, sc, p, Ap, 1);
-      hipLaunchKernelGGL(update_xr, dim3(nb), dim3(kRedThreads), 0, s, n, sc.S.as<double>(), x,
-                         r, p, Ap, sc.part.as<double>());
-      GP_CHECK_LAUNCH();
+  if (rr <= stop2) {
+    *iters = 0;
+    *rel_res = std::sqrt(rr / bb);
+    return GP_OK;
+  }
+  hipLaunchKernelGGL(cg_init_flags, dim3(1), dim3(64), 0, s, sc.S.as<double>(), stop2);
+  GP_CHECK_LAUNCH();
+  // Batches grow with the iteration count (at most 1/16 of the iterations
+  // done so far are queued beyond convergence) and stay short when an
+  // iteration is long enough that the host round trip does not matter.
+  int queued = 0, done_iters = 0, last_print = 0;
+  bool done = false;
+  double ms_per_iter = 0.0;
+  while (queued < max_iter) {
+    int cap = ms_per_iter > 1.0 ? 1 : (ms_per_iter > 0.25 ? 4 : 32);
+    int batch = std::max(1, std::min(cap, queued / 16));
+    batch = std::min(batch, max_iter - queued);
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int k = 0; k < batch; ++k) {
+      ++queued;
+      matvec_sorted(P, p, Ap, 1);
+      {
+        PhaseScope ps(P, PH_CG);
+        dot_into(P, sc, p, Ap, 1);
+        hipLaunchKernelGGL(update_xr, dim3(nb), dim3(kRedThreads), 0, s, n, sc.S.as<double>(), x,
+                           r, p, Ap, sc.part.as<double>());
+        GP_CHECK_LAUNCH();
+      }
+      if (replace_every > 0 && queued % replace_every == 0) {
+        matvec_sorted(P, x, Ap, 1);
+        hipLaunchKernelGGL(residual, dim3(nb), dim3(kRedThreads), 0, s, n, b, Ap, r);
+        hipLaunchKernelGGL(dot_partial, dim3(nb), dim3(kRedThreads), 0, s, n, r, r,
+                           sc.part.as<double>());
+        GP_CHECK_LAUNCH();
+      }
+      {
+        PhaseScope ps(P, PH_CG);
+        hipLaunchKernelGGL(dot_final, dim3(1), dim3(kRedThreads), 0, s, (int)nb,
+                           sc.part.as<double>(), sc.S.as<double>(), 0, 1);
+        hipLaunchKernelGGL(update_p, dim3(nb), dim3(kRedThreads), 0, s, n, sc.S.as<double>(), r, p);
+        GP_CHECK_LAUNCH();
+      }
     }
-    if (replace_every > 0 && it % replace_every == 0) {
-      matvec_sorted(P, x, Ap, 1);
-      hipLaunchKernelGGL(residual, dim3(nb), dim3(kRedThreads), 0, s, n, b, Ap, r);
-      hipLaunchKernelGGL(dot_partial, dim3(nb), dim3(kRedThreads), 0, s, n, r, r,
-                         sc.part.as<double>());
-      GP_CHECK_LAUNCH();
-    }
-    {
-      PhaseScope ps(P, PH_CG);
-      hipLaunchKernelGGL(dot_final, dim3(1), dim3(kRedThreads), 0, s, (int)nb,
-                         sc.part.as<double>(), sc.S.as<double>(), 0, 1);
-      hipLaunchKernelGGL(update_p, dim3(nb), dim3(kRedThreads), 0, s, n, sc.S.as<double>(), r, p);
-      GP_CHECK_LAUNCH();
-    }
-    rr = read_slot(P, sc, 2);
+    GP_HIP(hipMemcpyAsync(sc.hS, sc.S.as<double>(), 9 * sizeof(double), hipMemcpyDeviceToHost, s));
+    GP_HIP(hipStreamSynchronize(s));
+    ms_per_iter = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+                      .count() / batch;
+    rr = sc.hS[0];
+    done = sc.hS[7] != 0.0;
+    done_iters = (int)sc.hS[8];
     if (!std::isfinite(rr)) throw Error{GP_EDEVICE, "CG breakdown: non-finite residual"};
-    if (progress > 0 && it % progress == 0) {
-      std::fprintf(stderr, "[gpnufft] cg it=%d rel_res=%.3e\n", it, std::sqrt(rr / bb));
+    if (progress > 0 && done_iters / progress > last_print) {
+      last_print = done_iters / progress;
+      std::fprintf(stderr, "[gpnufft] cg it=%d rel_res=%.3e\n", done_iters, std::sqrt(rr / bb));
       std::fflush(stderr);
     }
+    if (done) break;
   }
-  *iters = it;
+  *iters = done_iters;
   *rel_res = std::sqrt(rr / bb);
-  return rr <= stop2 ? GP_OK : GP_ENOCONV;
+  return done ? GP_OK : GP_ENOCONV;
 }
 
 }  // namespace gp

@@ -7,7 +7,7 @@
 // window; everything else is zero), the last stage stores straight to HBM
 // (only the output window later steps read), and the stages in between
 // exchange data through LDS one real component at a time (a padded buffer of
-// L + L/32 reals per sequence, so two workgroups fit on a CU).  With radices
+// L + L/32 reals per sequence).  With radices
 // up to 32 an 8192-point transform is three stages and two exchanges.
 // Pruning both windows keeps the empty border of the oversampled grid (points
 // fill a fraction 2*Delta-omega of the period) and the discarded high
@@ -346,6 +346,19 @@ void launch_len(const FftPass& q, const void* in, void* out, const void* tw, hip
   p.L4 = q.L4 > 0 ? q.L4 : 1;
   p.tw4_mod = q.L4 > 0 ? (q.L4 / L) : 1;
   p.tw4_at_load = q.tw4_at_load;
+  // Long strided (column) transforms: two columns per workgroup, so pairs of
+  // adjacent lanes read adjacent elements of one cache line.
+  if constexpr (B == 1 && L >= 6144) {
+    if (q.inner > 1) {
+      const int64_t nb2 = (p.ntrans + 1) / 2;
+      if (nb2 <= 0) return;
+      hipLaunchKernelGGL((fft_pass_kernel<T, L, EPT, 2>), dim3((unsigned)nb2), dim3(2 * (L / EPT)),
+                         0, s, static_cast<const V*>(in), static_cast<V*>(out),
+                         static_cast<const V*>(tw), static_cast<const V*>(q.tw4), p);
+      GP_CHECK_LAUNCH();
+      return;
+    }
+  }
   const int64_t nblk = (p.ntrans + B - 1) / B;
   if (nblk <= 0) return;
   hipLaunchKernelGGL((fft_pass_kernel<T, L, EPT, B>), dim3((unsigned)nblk), dim3(B * (L / EPT)),

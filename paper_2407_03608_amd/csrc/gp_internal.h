@@ -77,6 +77,16 @@ struct Records {
   DevBuf cell;                // int32  [d][n] first window cell in the active box
   DevBuf pw;                  // T      [n][rs] window values and w_k
   DevBuf bin_start;           // int32  [n_bins + 1]
+  // Work lists that split crowded tiles into point chunks (built with the
+  // bin sort; see build_work_lists):
+  //  sp_work  int4 {tile, lo, hi, slot}: spread the tile's source points
+  //           [lo, hi) (positions in the tile's source sequence) into the
+  //           grid (slot < 0) or into partial tile `slot`
+  //  sp_red   int4 {tile, slot0, count, 0}: grid tile = sum of its partials,
+  //           added in slot order
+  //  in_work  int4 {bin, p_lo, p_hi, 0}: interpolate sorted points [p_lo, p_hi)
+  DevBuf sp_work, sp_red, in_work, part;
+  int64_t n_sp_work = 0, n_sp_red = 0, n_in_work = 0, n_slots = 0;
 };
 
 // ------------------------------------------------------------------- plan --
@@ -110,6 +120,7 @@ struct Plan {
   int tile[3] = {1, 1, 1};
   int nbins[3] = {1, 1, 1};
   int64_t n_bins = 1;
+  int nsrc = 2;               // source bins per dimension that reach a tile
   int fourstep = 0;           // d = 1 and nf > 8192: nf = L1 * L2
   int L1 = 0, L2 = 0;
   int nk = 0;                 // real grids = N_sigma + 1

@@ -18,6 +18,7 @@
 // the tile of their first window cell, so the sources are the 2^d (or more)
 // neighbouring bins), accumulates in LDS with LDS atomics and writes its tile
 // with plain coalesced stores.  No global atomics and no zero-fill pass.
+#include <climits>
 #include <cmath>
 #include <mutex>
 
@@ -70,10 +71,15 @@ __host__ __device__ constexpr int lds_stride(int rs) { return rs | 1; }
 // staged source point, adds its contribution to the grid pairs of the chunk in
 // registers when the point's window covers the cell.  No atomics, so the
 // summation order (and the result) is fixed.
+//
+// A crowded tile is split into chunks of its source points (work item
+// {tile, lo, hi, slot}); each chunk writes a partial tile to `part`, and
+// spread_reduce_kernel adds the partials in slot order.
 template <typename T, int D, int CPT>
 __global__ __launch_bounds__(kThreads) void spread_owner_kernel(
     NuArgs a, const double* __restrict__ x, const int* __restrict__ cell,
     const T* __restrict__ pw, int rs, const int* __restrict__ bin_start,
+    const int4* __restrict__ work, typename V2<T>::type* __restrict__ part,
     typename V2<T>::type* __restrict__ grid) {
   using V = typename V2<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -83,9 +89,12 @@ __global__ __launch_bounds__(kThreads) void spread_owner_kernel(
   T* s_x = s_rec + kPB * ls;                      // [kPB]
   int* s_cell = reinterpret_cast<int*>(s_x + kPB);  // [kPB][D]
 
+  // no work list: one item per tile, all of its sources, written to the grid
+  const int4 wk = work ? work[blockIdx.x] : make_int4((int)blockIdx.x, 0, INT_MAX, -1);
+  const int src_lo = wk.y, src_hi = wk.z, slot = wk.w;
   int tcoord[3] = {0, 0, 0}, t0[3] = {0, 0, 0};
   {
-    int64_t tb = blockIdx.x;
+    int64_t tb = wk.x;
     for (int r = 0; r < D; ++r) {
       tcoord[r] = (int)(tb % a.nbins[r]);
       tb /= a.nbins[r];
@@ -116,7 +125,8 @@ __global__ __launch_bounds__(kThreads) void spread_owner_kernel(
   const int wko = D * w + 2 * a.g0;
   int nsrc_tot = 1;
   for (int r = 0; r < D; ++r) nsrc_tot *= a.nsrc;
-  for (int sb = 0; sb < nsrc_tot; ++sb) {
+  int pos = 0;  // start of the current source bin in the tile's source sequence
+  for (int sb = 0; sb < nsrc_tot && pos < src_hi; ++sb) {
     int64_t bin = 0, mul = 1;
     bool ok = true;
     int q = sb;
@@ -128,7 +138,9 @@ __global__ __launch_bounds__(kThreads) void spread_owner_kernel(
       mul *= a.nbins[r];
     }
     if (!ok) continue;
-    const int p0 = bin_start[bin], p1 = bin_start[bin + 1];
+    const int b0 = bin_start[bin], cnt = bin_start[bin + 1] - b0;
+    const int p0 = b0 + max(src_lo - pos, 0), p1 = b0 + min(src_hi - pos, cnt);
+    pos += cnt;
     for (int pb = p0; pb < p1; pb += kPB) {
       const int np = min(kPB, p1 - pb);
       __syncthreads();
@@ -171,15 +183,57 @@ __global__ __launch_bounds__(kThreads) void spread_owner_kernel(
       }
     }
   }
-  // write my cells (the tile is exclusively owned)
+  // write my cells (the tile, or this chunk's partial tile, is exclusively owned)
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
     if (!mine[c]) continue;
+    if (slot >= 0) {
+      const int l = threadIdx.x + c * kThreads;
+#pragma unroll
+      for (int g = 0; g < kGC; ++g)
+        if (g < a.gc) part[((int64_t)slot * kGC + g) * tcells + l] = acc[c][g];
+      continue;
+    }
     const int64_t gi = a.grid_off + (int64_t)cx[c] * a.gstride[0] + (int64_t)cy[c] * a.gstride[1] +
                        (int64_t)cz[c] * a.gstride[2];
 #pragma unroll
     for (int g = 0; g < kGC; ++g)
       if (g < a.gc) grid[(int64_t)(a.g0 + g) * a.pair_stride + gi] = acc[c][g];
+  }
+}
+
+// Tiles split into chunks: grid tile = sum of the chunks' partial tiles, added
+// in chunk order.  One workgroup per split tile ({tile, slot0, count}).
+template <typename T, int D>
+__global__ __launch_bounds__(kThreads) void spread_reduce_kernel(
+    NuArgs a, const int4* __restrict__ red, const typename V2<T>::type* __restrict__ part,
+    typename V2<T>::type* __restrict__ grid) {
+  using V = typename V2<T>::type;
+  const int4 wk = red[blockIdx.x];
+  const int tc0 = a.tile[0], tc1 = D > 1 ? a.tile[1] : 1;
+  const int tcells = tc0 * tc1 * (D > 2 ? a.tile[2] : 1);
+  int t0[3] = {0, 0, 0};
+  {
+    int64_t tb = wk.x;
+    for (int r = 0; r < D; ++r) {
+      t0[r] = (int)(tb % a.nbins[r]) * a.tile[r];
+      tb /= a.nbins[r];
+    }
+  }
+  for (int e = threadIdx.x; e < a.gc * tcells; e += kThreads) {
+    const int g = e / tcells, l = e - g * tcells;
+    V v = V{T(0), T(0)};
+    for (int j = 0; j < wk.z; ++j) {
+      const V u = part[((int64_t)(wk.y + j) * kGC + g) * tcells + l];
+      v.x += u.x;
+      v.y += u.y;
+    }
+    const int c0 = t0[0] + l % tc0;
+    const int c1 = D > 1 ? t0[1] + (l / tc0) % tc1 : 0;
+    const int c2 = D > 2 ? t0[2] + l / (tc0 * tc1) : 0;
+    const int64_t gi = a.grid_off + (int64_t)c0 * a.gstride[0] + (int64_t)c1 * a.gstride[1] +
+                       (int64_t)c2 * a.gstride[2];
+    grid[(int64_t)(a.g0 + g) * a.pair_stride + gi] = v;
   }
 }
 
@@ -356,7 +410,7 @@ __global__ __launch_bounds__(kThreads) void interp_gather_kernel(
 template <typename T, int D>
 __global__ __launch_bounds__(kThreads) void interp_kernel(
     NuArgs a, const typename V2<T>::type* __restrict__ grid, const int* __restrict__ cell,
-    const T* __restrict__ pw, int rs, const int* __restrict__ bin_start,
+    const T* __restrict__ pw, int rs, const int4* __restrict__ work,
     const double* __restrict__ x, double* __restrict__ y) {
   using V = typename V2<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -375,12 +429,11 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(
   double* s_part = reinterpret_cast<double*>(s_rec + kPB * ls);  // [kPB][kGC] (8-B aligned)
   int* s_cell = reinterpret_cast<int*>(s_part + kPB * kGC);      // [kPB][D]
 
-  const int64_t bin = blockIdx.x;
-  const int p0 = bin_start[bin], p1 = bin_start[bin + 1];
-  if (p0 == p1) return;
+  const int4 wk = work[blockIdx.x];  // {bin, p_lo, p_hi}: one chunk of the bin's points
+  const int p0 = wk.y, p1 = wk.z;
   int t0[3] = {0, 0, 0};
   {
-    int64_t tb = bin;
+    int64_t tb = wk.x;
     for (int r = 0; r < D; ++r) {
       t0[r] = (int)(tb % a.nbins[r]) * a.tile[r];
       tb /= a.nbins[r];
@@ -518,8 +571,7 @@ NuArgs nu_args(const Plan* P) {
     a.pair_stride = (int64_t)P->na[0] * P->na[1] * P->na[2];
     a.grid_off = 0;
   }
-  a.nsrc = (P->w - 2) / P->tile[0] + 2;
-  for (int r = 1; r < P->d; ++r) a.nsrc = std::max(a.nsrc, (P->w - 2) / P->tile[r] + 2);
+  a.nsrc = P->nsrc;
   a.g0 = 0;
   a.gc = 0;
   a.eta2 = P->eta * P->eta;
@@ -543,11 +595,19 @@ void launch_spread_owner(Plan* P, const double* xs) {
   for (int ch = 0; ch < nch; ++ch) {
     a.g0 = ch * gc;
     a.gc = std::min(gc, P->npair - a.g0);
-    hipLaunchKernelGGL((spread_owner_kernel<T, D, CPT>), dim3((unsigned)P->n_bins), dim3(kThreads),
-                       spread_owner_smem<T>(P, R.rs), P->stream, a, xs, R.cell.as<int>(),
-                       R.pw.as<T>(), R.rs, R.bin_start.as<int>(),
+    hipLaunchKernelGGL((spread_owner_kernel<T, D, CPT>), dim3((unsigned)R.n_sp_work),
+                       dim3(kThreads), spread_owner_smem<T>(P, R.rs), P->stream, a, xs,
+                       R.cell.as<int>(), R.pw.as<T>(), R.rs, R.bin_start.as<int>(),
+                       R.n_sp_red > 0 ? R.sp_work.as<int4>() : nullptr,
+                       R.part.as<typename V2<T>::type>(),
                        P->gridA.as<typename V2<T>::type>());
     GP_CHECK_LAUNCH();
+    if (R.n_sp_red > 0) {
+      hipLaunchKernelGGL((spread_reduce_kernel<T, D>), dim3((unsigned)R.n_sp_red), dim3(kThreads), 0,
+                         P->stream, a, R.sp_red.as<int4>(), R.part.as<typename V2<T>::type>(),
+                         P->gridA.as<typename V2<T>::type>());
+      GP_CHECK_LAUNCH();
+    }
   }
 }
 
@@ -597,10 +657,11 @@ void launch_interp(Plan* P, const Records& R, const double* xs, double* ys, int 
     a.g0 = ch * gc;
     a.gc = std::min(gc, P->npair - a.g0);
     a.first_chunk = ch == 0;
-    hipLaunchKernelGGL((interp_kernel<T, D>), dim3((unsigned)P->n_bins), dim3(kThreads),
+    if (R.n_in_work == 0) break;
+    hipLaunchKernelGGL((interp_kernel<T, D>), dim3((unsigned)R.n_in_work), dim3(kThreads),
                        interp_smem<T>(P, a.gc, R.rs), P->stream, a,
                        g.as<typename V2<T>::type>(), R.cell.as<int>(), R.pw.as<T>(), R.rs,
-                       R.bin_start.as<int>(), xs, ys);
+                       R.in_work.as<int4>(), xs, ys);
     GP_CHECK_LAUNCH();
   }
 }

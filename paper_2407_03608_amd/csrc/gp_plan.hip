@@ -296,6 +296,112 @@ __global__ void atab_kernel(int64_t rows, int npk, int nkp, int nk, int nt,
 // training points at plan time and for posterior targets).
 struct Records;  // fwd (defined in nufft.hip via Plan buffers)
 
+// Chunk sizes of the work lists: at least a minimum, and large enough that
+// one launch has no more than about kTargetItems chunked items.
+constexpr int64_t kTargetItems = 2048;
+constexpr int64_t kMinSpreadChunk = 256;
+constexpr int64_t kMinInterpChunk = 64;
+constexpr int kSlotPairs = 8;  // pairs per partial slot (the spread pair-chunk size)
+
+static int64_t source_total_bound(const Plan* P, int64_t n) {
+  int64_t m = 1;
+  for (int r = 0; r < P->d; ++r) m *= P->nsrc;
+  return n * m;
+}
+
+// Device bytes of the work lists and partial tiles, bounded before the bin
+// sort is known (plan query) by the chunk-size rule.
+size_t work_list_bound_bytes(const Plan* P, int64_t n, size_t cs) {
+  const int64_t ts = source_total_bound(P, n);
+  const int64_t qs = std::max(kMinSpreadChunk, ts / kTargetItems);
+  const int64_t slots = std::min<int64_t>(2 * kTargetItems + 2, 2 * ts / qs + 2);
+  const int64_t tcells = (int64_t)P->tile[0] * P->tile[1] * P->tile[2];
+  const int64_t items = P->n_bins + ts / qs + 1;
+  const int64_t qi = std::max(kMinInterpChunk, n / kTargetItems);
+  const int64_t iitems = P->n_bins + n / qi + 1;
+  return (size_t)(2 * items + iitems) * 16 + (size_t)slots * tcells * kSlotPairs * cs;
+}
+
+// Build the spread and interpolation work lists from the bin offsets.  The
+// source sequence of a tile is the concatenation of its source bins in the
+// order the spread kernel visits them (offset q along each dimension, the
+// first dimension fastest; bins before the grid start are skipped).
+static void build_work_lists(Plan* P, Records& R, const std::vector<int>& start, size_t cs) {
+  const int d = P->d, nsrc = P->nsrc;
+  int nsrc_tot = 1;
+  for (int r = 0; r < d; ++r) nsrc_tot *= nsrc;
+  std::vector<int64_t> src(P->n_bins);
+  int64_t ts = 0;
+  for (int64_t t = 0; t < P->n_bins; ++t) {
+    int tc[3] = {0, 0, 0};
+    int64_t tb = t;
+    for (int r = 0; r < d; ++r) {
+      tc[r] = (int)(tb % P->nbins[r]);
+      tb /= P->nbins[r];
+    }
+    int64_t cnt = 0;
+    for (int sb = 0; sb < nsrc_tot; ++sb) {
+      int64_t bin = 0, mul = 1;
+      bool ok = true;
+      int q = sb;
+      for (int r = 0; r < d; ++r) {
+        const int br = tc[r] - (q % nsrc);
+        q /= nsrc;
+        if (br < 0) ok = false;
+        bin += (int64_t)br * mul;
+        mul *= P->nbins[r];
+      }
+      if (ok) cnt += start[bin + 1] - start[bin];
+    }
+    src[t] = cnt;
+    ts += cnt;
+  }
+  const int64_t qs = std::max(kMinSpreadChunk, ts / kTargetItems);
+  std::vector<int> spw, spr;
+  int64_t slots = 0;
+  for (int64_t t = 0; t < P->n_bins; ++t) {
+    const int64_t c = std::max<int64_t>(1, (src[t] + qs - 1) / qs);
+    if (c == 1) {
+      spw.insert(spw.end(), {(int)t, 0, (int)src[t], -1});
+      continue;
+    }
+    // equal chunks
+    for (int64_t j = 0; j < c; ++j)
+      spw.insert(spw.end(), {(int)t, (int)(src[t] * j / c), (int)(src[t] * (j + 1) / c),
+                             (int)(slots + j)});
+    spr.insert(spr.end(), {(int)t, (int)slots, (int)c, 0});
+    slots += c;
+  }
+  const int64_t qi = std::max(kMinInterpChunk, R.n / kTargetItems);
+  std::vector<int> inw;
+  for (int64_t b = 0; b < P->n_bins; ++b) {
+    const int64_t cnt = start[b + 1] - start[b];
+    if (cnt == 0) continue;
+    const int64_t c = (cnt + qi - 1) / qi;
+    for (int64_t j = 0; j < c; ++j)
+      inw.insert(inw.end(), {(int)b, (int)(start[b] + cnt * j / c), (int)(start[b] + cnt * (j + 1) / c), 0});
+  }
+  hipStream_t s = P->stream;
+  R.n_sp_work = (int64_t)spw.size() / 4;
+  R.n_sp_red = (int64_t)spr.size() / 4;
+  R.n_in_work = (int64_t)inw.size() / 4;
+  R.n_slots = slots;
+  R.sp_work.alloc(spw.size() * sizeof(int));
+  GP_HIP(hipMemcpyAsync(R.sp_work.p, spw.data(), spw.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  if (!spr.empty()) {
+    R.sp_red.alloc(spr.size() * sizeof(int));
+    GP_HIP(hipMemcpyAsync(R.sp_red.p, spr.data(), spr.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    const int64_t tcells = (int64_t)P->tile[0] * P->tile[1] * P->tile[2];
+    R.part.alloc((size_t)slots * tcells * kSlotPairs * cs);
+  }
+  if (!inw.empty()) {
+    R.in_work.alloc(inw.size() * sizeof(int));
+    GP_HIP(hipMemcpyAsync(R.in_work.p, inw.data(), inw.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  }
+  // the host vectors are released when this returns: wait for the copies
+  GP_HIP(hipStreamSynchronize(s));
+}
+
 void build_records_into(Plan* P, int64_t n, const double* pts, const double* sig,
                         const double* l, Records& R, int* out_of_box) {
   hipStream_t s = P->stream;
@@ -352,6 +458,7 @@ void build_records_into(Plan* P, int64_t n, const double* pts, const double* sig
   GP_HIP(hipMemcpyAsync(R.bin_start.p, start.data(), (P->n_bins + 1) * sizeof(int),
                         hipMemcpyHostToDevice, s));
   GP_HIP(hipMemcpyAsync(posd.p, hpos.data(), n * sizeof(int), hipMemcpyHostToDevice, s));
+  build_work_lists(P, R, start, P->precision == GP_FP64 ? 16 : 8);
 #define GP_SCATTER(T)                                                                            \
   hipLaunchKernelGGL(scatter_records_kernel<T>, dim3(nb), dim3(bs), 0, s, d, n, P->w, P->beta, \
                      P->nk, P->nkp, R.rs, posd.as<int>(), cell_tmp.as<int>(),                  \
@@ -596,6 +703,10 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
     P->nbins[r] = na / tl;
   }
   P->n_bins = (int64_t)P->nbins[0] * P->nbins[1] * P->nbins[2];
+  // a point's window starts in its own tile and reaches at most nsrc - 1
+  // tiles further along each dimension
+  P->nsrc = 2;
+  for (int r = 0; r < d; ++r) P->nsrc = std::max(P->nsrc, (P->w - 2) / P->tile[r] + 2);
   P->nk = P->n_sigma + 1;
   P->npair = (P->nk + 1) / 2;
 
@@ -656,6 +767,7 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
   bytes += (size_t)G * (szA + szB + szB2 + szC) * cs;
   bytes += (size_t)n * (sizeof(int) * (1 + d) + ts * (d * P->w + P->nk + 1));
   bytes += (size_t)(P->n_bins + 1) * sizeof(int);
+  bytes += work_list_bound_bytes(P, n, cs);
   if (P->step3 == 0)
     bytes += (size_t)P->a_rows * (P->nkp * (P->nkp + 1) / 2) * ts + rowmap.size() * sizeof(int);
   else

@@ -29,7 +29,7 @@ struct SRequest {
   double nu = 0, eta = 0;
   size_t bytes = 0;
   double t_submit = 0, t_start = -1, t_done = -1;
-  int status = GP_OK, iters = 0, refinements = 0, slot = -1;
+  int status = GP_OK, iters = 0, refinements = 0, slot = -1, precision = GP_FP64;
   double rel_res = 0;
   bool done = false;
   std::string err;
@@ -62,14 +62,15 @@ void fill_opts(const Server& S, int bulk, hipStream_t st, gp_opts* o) {
   o->stream = st;
 }
 
-// Device bytes the request's plan(s) will hold.
-size_t request_bytes(Server& S, const SRequest& r) {
+// Device bytes the request's plan(s) will hold; decides the precision path.
+size_t request_bytes(Server& S, SRequest& r) {
   gp_opts o;
   size_t b64 = 0, b32 = 0;
   fill_opts(S, 0, S.qstream, &o);
   Plan q64;
   build_plan(r.d, r.n, r.pts, r.sigma, r.l, r.nu, r.eta, S.o.plan_tol, &o, &q64, true, &b64);
-  if (S.o.precision == GP_FP64) return b64;
+  r.precision = (S.o.precision == GP_FP64 || b64 < S.o.fp64_below_bytes) ? GP_FP64 : GP_FP32_BULK;
+  if (r.precision == GP_FP64) return b64;
   fill_opts(S, 1, S.qstream, &o);
   o.dw = q64.dw;
   o.M = q64.M;
@@ -83,7 +84,7 @@ void run_request(Server& S, SRequest& r, hipStream_t st) {
   fill_opts(S, 0, st, &o);
   Plan P64;
   build_plan(r.d, r.n, r.pts, r.sigma, r.l, r.nu, r.eta, S.o.plan_tol, &o, &P64, false, nullptr);
-  if (S.o.precision == GP_FP64) {
+  if (r.precision == GP_FP64) {
     double* V = P64.vec.as<double>();
     gather_sorted(&P64, r.y, V + 6 * r.n);
     GP_HIP(hipMemsetAsync(V + 2 * r.n, 0, r.n * sizeof(double), st));
@@ -192,6 +193,7 @@ int gp_server_opts_init(gp_server_opts* o) {
   o->inner_tol = 3e-3;
   o->max_iter = 20000;
   o->max_refine = 10;
+  o->fp64_below_bytes = (size_t)256 << 20;
   return GP_OK;
 }
 
@@ -275,6 +277,7 @@ static void fill_info(const SRequest& r, gp_request_info* info) {
   info->t_done = r.t_done;
   info->device_bytes = r.bytes;
   info->slot = r.slot;
+  info->precision = r.precision;
 }
 
 int gp_server_wait(gp_server_t h, int64_t id, gp_request_info* info) {

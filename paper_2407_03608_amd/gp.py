@@ -141,6 +141,7 @@ class GpServerOpts(ctypes.Structure):
         ("inner_tol", _c_d),
         ("max_iter", _c_i),
         ("max_refine", _c_i),
+        ("fp64_below_bytes", _c_sz),
     ]
 
 
@@ -155,6 +156,7 @@ class GpRequestInfo(ctypes.Structure):
         ("t_done", _c_d),
         ("device_bytes", _c_sz),
         ("slot", _c_i),
+        ("precision", _c_i),
     ]
 
 

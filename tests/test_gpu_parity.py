@@ -163,6 +163,44 @@ def test_add_noise_and_linearity(gp):
     assert abs(u @ kv - ku @ v) < 1e-10 * abs(u @ kv)
 
 
+@pytest.mark.parametrize("d,n,M,prec", [(1, 20000, 120, 0), (1, 20000, 120, 1), (2, 20000, 20, 0),
+                                         (2, 20000, 20, 1), (3, 12000, 6, 1)])
+def test_matvec_dense_points_split_tiles(gp, d, n, M, prec):
+    """Many points on a small grid: tiles hold far more points than one chunk,
+    so spreading writes partial tiles that are added in order, and
+    interpolation runs several workgroups per tile."""
+    prob = inputs.random_small(d, n, seed=40 + d, nu=1.5, lmin=0.2, lmax=0.4)
+    tol, bar = (1e-8, FP64_TOL) if prec == 0 else (1e-4, FP32_TOL)
+    P, info, a, got, _ = _check_matvec(gp, prob, tol=tol, precision=prec, bar=bar, M=M)
+    per_tile = n / np.prod([info["na"][r] // info["tile"][r] for r in range(d)])
+    say(f"  points per tile {per_tile:.0f}")
+    assert per_tile > 300
+    # deterministic: a second matvec gives the same bits
+    assert np.array_equal(host(P.matvec(cuda(a))), got)
+
+
+def test_cg_device_stopping_test_matches_iteration_count(gp):
+    """The stopping test runs on the device: a solve that converges after K
+    iterations returns the same iterate as one capped at max_iter = K, and a
+    cap of K - 1 reports non-convergence after exactly K - 1 iterations."""
+    prob = inputs.random_small(2, 500, seed=8, nu=1.5, lmin=0.1, lmax=0.2, eta=0.05)
+    P = _plan(gp, prob, tol=1e-8, M=20)
+    y = cuda(prob.y)
+    a1, i1 = P.cg_solve(y, tol=1e-8, max_iter=5000)
+    K = i1["iters"]
+    say(f"  converged after {K} iterations, rel {i1['rel_res']:.3e}")
+    assert i1["status"] == 0 and K > 40 and i1["rel_res"] <= 1e-8
+    a2, i2 = P.cg_solve(y, tol=1e-8, max_iter=K)
+    assert i2["status"] == 0 and i2["iters"] == K
+    assert np.array_equal(host(a1), host(a2))
+    a3, i3 = P.cg_solve(y, tol=1e-8, max_iter=K - 1)
+    assert i3["status"] == gp.GP_ENOCONV and i3["iters"] == K - 1 and i3["rel_res"] > 1e-8
+    # with residual replacement too
+    a4, i4 = P.cg_solve(y, tol=1e-8, max_iter=5000, replace_every=7)
+    a5, i5 = P.cg_solve(y, tol=1e-8, max_iter=i4["iters"], replace_every=7)
+    assert i5["iters"] == i4["iters"] and np.array_equal(host(a4), host(a5))
+
+
 def test_cg_matches_cholesky_of_ktilde(gp):
     prob = inputs.random_small(2, 300, seed=21, nu=1.5, lmin=0.1, lmax=0.2, eta=0.3)
     P = _plan(gp, prob, tol=1e-10, M=22)

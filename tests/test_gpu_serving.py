@@ -70,6 +70,25 @@ def test_server_alone_vs_mix(gp):
         assert np.array_equal(aa, host(am))
 
 
+def test_server_precision_routing(gp):
+    """Small operators are solved in fp64 directly; with the threshold at zero
+    every request takes the fp32-bulk refined path; both reach the tolerance."""
+    probs = _requests(3)
+    dev = [(cuda(p.x), cuda(p.sigma), cuda(p.l), cuda(p.y)) for p in probs]
+    out = {}
+    for thr in (1 << 40, 0):
+        S = gp.Server(max_slots=2, max_iter=6000, fp64_below_bytes=thr)
+        ids = [S.submit(x, s, l, p.nu, p.eta, y) for p, (x, s, l, y) in zip(probs, dev)]
+        out[thr] = [S.wait(i) for i in ids]
+        S.close()
+    for (a64, i64), (a32, i32) in zip(out[1 << 40], out[0]):
+        say(f"  fp64 iters={i64['iters']} rel={i64['rel_res']:.2e} | fp32-bulk iters={i32['iters']} "
+            f"passes={i32['refinements']} rel={i32['rel_res']:.2e}")
+        assert i64["precision"] == gp.GP_FP64 and i32["precision"] == gp.GP_FP32_BULK
+        assert i64["status"] == 0 and i32["status"] == 0
+        assert i64["rel_res"] <= 1e-6 and i32["rel_res"] <= 1e-6
+
+
 def test_server_rejects_oversized_and_bad_requests(gp):
     p = _requests(1)[0]
     S = gp.Server(max_slots=2, max_device_bytes=1 << 20)
