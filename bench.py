@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="end with one device copy of this size (HBM counter calibration)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the secondary workloads (d=1 N=2000, d=3 N=1e7)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serving", action="store_true", help="serving benchmark instead of matvec steps")
     ap.add_argument("--requests", type=int, default=512)
@@ -55,6 +57,8 @@ def parse():
     ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--serve-bytes-gib", type=float, default=200.0)
     ap.add_argument("--serve-max-iter", type=int, default=20000)
+    ap.add_argument("--policy", choices=["smallest", "fifo"], default="smallest",
+                    help="admission order of queued requests")
     return ap.parse_args()
 
 
@@ -113,6 +117,36 @@ def time_path(gp, torch, P, y, steps, warmup):
     return (t1 - t0), tm
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "matern_2d_hbm_counters.md")
+
+
+def kernel_sources_sha256() -> str:
+    """Hash of the HIP sources; the counter summary records the hash it was taken at."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2407_03608_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(d, "*.hip")) + glob.glob(os.path.join(d, "*.h"))):
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(precision: str, kernel: str):
+    """HBM bytes per matvec of `kernel` from the committed counter summary, or
+    None when there is none or it was taken on other kernel sources."""
+    try:
+        txt = open(TRAFFIC_FILE).read()
+        blk = txt.split("```json", 1)[1].split("```", 1)[0]
+        data = json.loads(blk)
+    except (OSError, IndexError, ValueError):
+        return None
+    if data.get("sources_sha256") != kernel_sources_sha256():
+        return None
+    k = data.get("per_matvec_bytes", {}).get(precision, {}).get(kernel)
+    return None if k is None else k["read"] + k["write"]
+
+
 def roofline(info, tm, steps):
     best = None
     for name, (launches, ms) in tm.items():
@@ -124,9 +158,61 @@ def roofline(info, tm, steps):
     name, ms = best
     b = alg_bytes(info, name)
     achieved = b / (ms * 1e-3) / 1e9
+    prec = "fp64" if info["precision"] == 0 else "fp32"
+    tr = measured_traffic(prec, name) if info["d"] == 2 and info["n"] == 1_000_000 else None
     return {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None if tr is None else round(tr / 1e9, 4), "traffic_unit": "GB per launch group",
             "avg_ms": round(ms, 4), "alg_bytes": b}
+
+
+def secondary_workloads(gp, torch, args):
+    """The other measured configurations, reported beside the headline:
+    d=1 N=2000 nu=3/2 fp64 (launch-bound; full solve to 1e-8) and d=3 N=1e7
+    Gaussian-mixture nu=5/2 in fp32-bulk (spreading-heavy)."""
+    from paper_2407_03608_amd import inputs
+    out = {}
+    dev = "cuda"
+    log("secondary: matern_1d")
+    p1 = inputs.matern_1d()
+    X, S, L, Y = (torch.as_tensor(v).to(dev) for v in (p1.x, p1.sigma, p1.l, p1.y))
+    P = gp.Plan(X, S, L, p1.nu, p1.eta, 1e-8)
+    info = P.info()
+    t, tm = time_path(gp, torch, P, Y, 200, 20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, ci = P.cg_solve(Y, tol=1e-8, max_iter=20000)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    out["matern_1d_fp64"] = {
+        "workload": "d=1 N=2000 nu=3/2 sigma=1+0.5 sin 2 pi x, l=0.05+0.03 cos 2 pi x, eta=0.1, fp64 tol 1e-8",
+        "ms_per_step": round(1e3 * t / 200, 4), "points_per_s": round(p1.n * 200 / t, 1),
+        "solve_1e-8": {"seconds": round(ts, 4), "iters": ci["iters"], "status": ci["status"]},
+        "kernels_ms": {k: round(v[1] / 200, 4) for k, v in tm.items() if v[0]},
+        "plan": {k: info[k] for k in ("n_sigma", "n_t", "dw", "M", "nf", "w")}}
+    P.close()
+    del X, S, L, Y
+    log("secondary: matern_3d fp32-bulk")
+    p3 = inputs.matern_3d()
+    X, S, L, Y = (torch.as_tensor(v).to(dev) for v in (p3.x, p3.sigma, p3.l, p3.y))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P = gp.Plan(X, S, L, p3.nu, p3.eta, 1e-4, precision=gp.GP_FP32_BULK)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    info = P.info()
+    steps = 10
+    t, tm = time_path(gp, torch, P, Y, steps, 2)
+    rf = roofline(info, tm, steps)
+    out["matern_3d_fp32_bulk"] = {
+        "workload": "d=3 N=1e7 8-component Gaussian mixture clipped to [0,1]^3, nu=5/2, sigma=1, "
+                    "l=0.03+0.02|x-0.5|, eta=0.1, fp32-bulk tol 1e-4",
+        "ms_per_step": round(1e3 * t / steps, 4), "points_per_s": round(p3.n * steps / t, 1),
+        "roofline": rf, "kernels_ms": {k: round(v[1] / steps, 4) for k, v in tm.items() if v[0]},
+        "plan_seconds": round(tp, 3),
+        "plan": {k: info[k] for k in ("n_sigma", "n_t", "dw", "M", "nf", "w", "na", "n_pairs", "device_bytes")}}
+    P.close()
+    return out
 
 
 def cpu_baseline(prob, seconds):
@@ -170,7 +256,8 @@ def serving(args):
                          for v in (p.x, p.sigma, p.l, p.y)))
     torch.cuda.synchronize()
     S = gp.Server(max_slots=args.slots, max_device_bytes=int(args.serve_bytes_gib * (1 << 30)),
-                  precision=gp.GP_FP32_BULK, max_iter=args.serve_max_iter)
+                  precision=gp.GP_FP32_BULK, max_iter=args.serve_max_iter,
+                  policy=gp.GP_SERVE_SMALLEST if args.policy == "smallest" else gp.GP_SERVE_FIFO)
     # warm-up: one small request end to end (kernel loading, first allocations)
     w = inputs.random_small(2, 2000, seed=9, nu=1.5, lmin=0.05, lmax=0.1)
     wid = S.submit(*(torch.as_tensor(v).to("cuda") for v in (w.x, w.sigma, w.l)), w.nu, w.eta,
@@ -230,7 +317,8 @@ def serving(args):
         "data": "synthetic (seeded request stream)",
         "config": {"workload": f"serving: {len(reqs)} requests, Poisson {args.rate}/s, d in {{1,2}}, "
                                "N log-uniform [1e3,5e5], nu in {1/2,3/2,5/2}, fp32-bulk + fp64 refinement, "
-                               "CG 1e-6", "slots": args.slots, "max_iter": args.serve_max_iter},
+                               "CG 1e-6", "slots": args.slots, "max_iter": args.serve_max_iter,
+                   "policy": args.policy},
         "serving": {"p50_s": round(float(np.percentile(lat, 50)), 4),
                     "p90_s": round(float(np.percentile(lat, 90)), 4),
                     "p99_s": round(float(np.percentile(lat, 99)), 4),
@@ -241,6 +329,7 @@ def serving(args):
                     "peak_running": st["peak_running"],
                     "peak_bytes": st["peak_bytes"],
                     "nonconverged": nonconv,
+                    "fp64_routed": int(sum(results[k]["precision"] == gp.GP_FP64 for k in range(len(reqs)))),
                     "iters_p50": int(np.percentile(iters, 50)),
                     "iters_max": int(iters.max()),
                     "points_total": int(sum(r.problem.n for r in reqs))},
@@ -355,6 +444,10 @@ def main():
                                   "rel_diff_vs_fp64_solution":
                                       float(torch.linalg.norm(al32 - al64) / torch.linalg.norm(al64))},
         }
+
+    if not args.no_extra:
+        P32.close()
+        out["workloads"] = secondary_workloads(gp, torch, args)
 
     if not args.no_cpu:
         log("cpu baseline")

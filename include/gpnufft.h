@@ -77,9 +77,11 @@ typedef struct {
   int spread;               /* type-1 spreading: 0 = each thread owns grid cells and sums
                                in registers (deterministic, default); 1 = per-(point, row)
                                work items with LDS atomics */
-  int interp;               /* type-2 interpolation: 0 = the bin's tile plus halo staged in
-                               LDS, (point, window row, pair) items (default); 1 = one thread
-                               per point reading its window through the caches */
+  int interp;               /* type-2 interpolation: 0 = default (d = 2: 2x2-bin tiles plus
+                               halo staged in LDS one grid pair at a time; d = 1, 3: as 2);
+                               1 = one thread per point reading its window through the
+                               caches; 2 = each bin's tile plus halo staged in LDS for a
+                               chunk of grid pairs, (point, window row, pair) items */
   int step3;                /* step 3 of section 4.2 (rem:step3): 0 = precomputed tensor
                                A_k'k, stored once per distinct |n|^2 (default); 1 = direct
                                sum over the t nodes at every mode */
@@ -174,6 +176,21 @@ int gp_cg_solve_refined(gp_plan_t inner, gp_plan_t outer, const double* y, doubl
 int gp_posterior_mean(gp_plan_t plan, const double* alpha, int64_t m, const double* targets,
                       const double* sigma_t, const double* l_t, double* mu);
 
+/* Posterior covariance eq:postcov at m targets (m x d device fp64, scales
+ * sigma_t, l_t as for gp_posterior_mean):
+ *   Sigma(x*_i, x*_j) = K~(x*_i, x*_j) - K~(x*_i, X) (K~ + eta^2 I)^{-1} K~(X, x*_j),
+ * every term with the plan's operator K~ (so Sigma is the Schur complement of
+ * a positive semidefinite matrix).  One CG solve per target (tolerance tol,
+ * at most max_iter iterations each) plus two operator applications.
+ * cov: m x m row-major device fp64 (column j from solve j; symmetric up to the
+ * CG tolerance), or NULL; var: the m variances Sigma(x*_j, x*_j), or NULL (not
+ * both NULL).  info: total iterations over the solves, the worst final
+ * relative residual, GP_ENOCONV if any solve stopped at max_iter (outputs are
+ * then still written).  Same target rules and errors as gp_posterior_mean. */
+int gp_posterior_cov(gp_plan_t plan, int64_t m, const double* targets, const double* sigma_t,
+                     const double* l_t, double tol, int max_iter, double* cov, double* var,
+                     gp_cg_info* info);
+
 /* ||y - (K~ + eta^2 I) alpha|| / ||y|| with the plan's operator (the true
  * residual of eq:gprsolve).  Synchronises the plan's stream. */
 int gp_residual(gp_plan_t plan, const double* y, const double* alpha, double* rel_res);
@@ -195,10 +212,13 @@ int gp_plan_get_timing(gp_plan_t plan, gp_timing* out);
 /* ------------------------------------------------------------- serving -----
  * Continuous batching of many independent GPR solves (each request: its own
  * points, scales, nu, eta and y).  The server runs max_slots worker threads,
- * each with its own HIP stream.  Requests are admitted in arrival order as
- * soon as a slot is free and the device bytes of the request's plans fit in
- * max_device_bytes next to the requests in flight; their solves overlap on the
- * device.  With precision GP_FP32_BULK a request is solved by fp32-bulk CG
+ * each with its own HIP stream.  A free slot admits a queued request whose
+ * plans' device bytes fit in max_device_bytes next to the requests in flight
+ * (or any request when none is in flight): with GP_SERVE_FIFO the oldest
+ * (waiting while it does not fit), with GP_SERVE_SMALLEST the one with the
+ * smallest bytes - aging_bytes_per_s x (seconds waited), so small requests
+ * pass large ones but a waiting request gains priority over time.  Admitted
+ * solves overlap on the device.  With precision GP_FP32_BULK a request is solved by fp32-bulk CG
  * inside fp64 iterative refinement (two plans, as gp_cg_solve_refined),
  * unless its fp64 plan needs fewer than fp64_below_bytes of device memory (a
  * small operator whose matvec is bound by launch latency, where the fp32 grids
@@ -207,6 +227,8 @@ int gp_plan_get_timing(gp_plan_t plan, gp_timing* out);
  * alpha) must stay valid until the request completes; alpha receives the
  * solution in the caller's point order. */
 typedef struct gp_server_s* gp_server_t;
+#define GP_SERVE_FIFO 0
+#define GP_SERVE_SMALLEST 1
 typedef struct {
   int max_slots;            /* requests in flight at once (1..64) */
   size_t max_device_bytes;  /* admission budget for the plans of the requests in flight */
@@ -218,6 +240,8 @@ typedef struct {
   int max_iter;             /* CG iterations per request, all passes (default 20000) */
   int max_refine;           /* refinement passes (default 10) */
   size_t fp64_below_bytes;  /* fp64 CG for requests whose fp64 plan is smaller (default 256 MiB) */
+  int policy;               /* GP_SERVE_SMALLEST (default) or GP_SERVE_FIFO */
+  double aging_bytes_per_s; /* priority gained per second of waiting (default 1 GiB/s) */
 } gp_server_opts;
 typedef struct {
   int status;               /* GP_OK, GP_ENOCONV or an error code */

@@ -221,6 +221,24 @@ def posterior_mean_exact(x, sig, l, nu, alpha, xt, sig_t, l_t) -> np.ndarray:
     return mu
 
 
+def _schur(Kxx, Kxs, Kss, eta) -> np.ndarray:
+    """Kss - Kxs^T (Kxx + eta^2 I)^{-1} Kxs, one oracle Cholesky solve per column."""
+    A = np.array(Kxx, dtype=np.float64, copy=True)
+    A[np.diag_indices_from(A)] += eta * eta
+    L = cholesky(A)
+    V = np.stack([chol_solve(L, np.ascontiguousarray(Kxs[:, j])) for j in range(Kxs.shape[1])], axis=1)
+    return np.asarray(Kss) - np.asarray(Kxs).T @ V
+
+
+def posterior_cov_exact(x, sig, l, nu, eta, xt, sig_t, l_t) -> np.ndarray:
+    """Posterior covariance eq:postcov at the targets with the exact kernel:
+    K(X*,X*) - K(X*,X) (K + eta^2 I)^{-1} K(X,X*)."""
+    Kxx = kernel_matrix(x, sig, l, nu)
+    Kxs = kernel_matrix(x, sig, l, nu, xt, sig_t, l_t)
+    Kss = kernel_matrix(xt, sig_t, l_t, nu)
+    return _schur(Kxx, Kxs, Kss, eta)
+
+
 # ------------------------------------------------------------ K-tilde O2 ----
 
 def tgrid(p: Params):
@@ -284,3 +302,13 @@ def ktilde_entries(p: Params, x, sig, l, y=None, sig_y=None, l_y=None) -> np.nda
     if rc:
         raise RuntimeError(f"orc_ktilde_entries failed: {rc}")
     return K
+
+
+def ktilde_posterior_cov(p: Params, x, sig, l, eta, xt, sig_t, l_t) -> np.ndarray:
+    """eq:postcov with the approximate operator K~ in every term (entries by the
+    theta-sum form)."""
+    Kxx = ktilde_entries(p, x, sig, l)
+    Kxs = ktilde_entries(p, x, sig, l, xt, sig_t, l_t)
+    Kss = ktilde_entries(p, xt, sig_t, l_t)
+    return _schur(Kxx, Kxs, Kss, eta)
+

@@ -225,7 +225,7 @@ int gp_plan_info(gp_plan_t h, gp_plan_params* o) {
     o->m_capped = P.m_capped;
     o->step3 = P.step3;
     o->spread = P.spread_owner ? 0 : 1;
-    o->interp = P.interp_gather ? 1 : 0;
+    o->interp = P.interp_mode;
     o->a_rows = P.a_rows;
     return GP_OK;
   });
@@ -301,35 +301,125 @@ int gp_cg_solve_refined(gp_plan_t hin, gp_plan_t hout, const double* y, double* 
   });
 }
 
+// Targets must lie in the plan's box and length-scale range (host check).
+static void validate_targets(Plan* P, int64_t m, const double* targets, const double* sigma_t,
+                             const double* l_t) {
+  std::vector<double> hx(m * P->d), hl(m), hs(m);
+  GP_HIP(hipMemcpyAsync(hx.data(), targets, m * P->d * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+  GP_HIP(hipMemcpyAsync(hl.data(), l_t, m * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+  GP_HIP(hipMemcpyAsync(hs.data(), sigma_t, m * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+  GP_HIP(hipStreamSynchronize(P->stream));
+  for (int64_t i = 0; i < m; ++i) {
+    for (int r = 0; r < P->d; ++r) {
+      double xp = (hx[i * P->d + r] - P->center[r]) * P->scale;
+      if (!std::isfinite(xp)) throw Error{GP_EDOMAIN, "non-finite target"};
+      if (xp < -1.0 - 1e-12 || xp > 1.0 + 1e-12) throw Error{GP_ERANGE, "target outside the plan's box"};
+    }
+    if (!(hs[i] > 0) || !(hl[i] > 0)) throw Error{GP_EDOMAIN, "target scales must be > 0"};
+    double sp = hl[i] * P->scale * 0.70710678118654752440;
+    if (P->n_sigma > 0 && (sp < P->s_min * (1 - 1e-12) || sp > P->s_max * (1 + 1e-12)))
+      throw Error{GP_ERANGE, "target length scale outside the plan's range"};
+    if (P->n_sigma == 0 && std::fabs(sp - P->s_min) > 1e-12 * P->s_min)
+      throw Error{GP_ERANGE, "stationary plan: target length scale differs"};
+  }
+}
+
 int gp_posterior_mean(gp_plan_t h, const double* alpha, int64_t m, const double* targets,
                       const double* sigma_t, const double* l_t, double* mu) {
   return guarded([&] {
     if (!h || !alpha || !targets || !sigma_t || !l_t || !mu) throw Error{GP_EINVAL, "null argument"};
     if (m < 1) throw Error{GP_EINVAL, "m must be >= 1"};
     Plan* P = &h->P;
-    // validate targets against the box and the length-scale range (host copy)
-    std::vector<double> hx(m * P->d), hl(m), hs(m);
-    GP_HIP(hipMemcpyAsync(hx.data(), targets, m * P->d * sizeof(double), hipMemcpyDeviceToHost, P->stream));
-    GP_HIP(hipMemcpyAsync(hl.data(), l_t, m * sizeof(double), hipMemcpyDeviceToHost, P->stream));
-    GP_HIP(hipMemcpyAsync(hs.data(), sigma_t, m * sizeof(double), hipMemcpyDeviceToHost, P->stream));
-    GP_HIP(hipStreamSynchronize(P->stream));
-    for (int64_t i = 0; i < m; ++i) {
-      for (int r = 0; r < P->d; ++r) {
-        double xp = (hx[i * P->d + r] - P->center[r]) * P->scale;
-        if (!std::isfinite(xp)) throw Error{GP_EDOMAIN, "non-finite target"};
-        if (xp < -1.0 - 1e-12 || xp > 1.0 + 1e-12) throw Error{GP_ERANGE, "target outside the plan's box"};
-      }
-      if (!(hs[i] > 0) || !(hl[i] > 0)) throw Error{GP_EDOMAIN, "target scales must be > 0"};
-      double sp = hl[i] * P->scale * 0.70710678118654752440;
-      if (P->n_sigma > 0 && (sp < P->s_min * (1 - 1e-12) || sp > P->s_max * (1 + 1e-12)))
-        throw Error{GP_ERANGE, "target length scale outside the plan's range"};
-      if (P->n_sigma == 0 && std::fabs(sp - P->s_min) > 1e-12 * P->s_min)
-        throw Error{GP_ERANGE, "stationary plan: target length scale differs"};
-    }
+    validate_targets(P, m, targets, sigma_t, l_t);
     double* xs = P->vec.as<double>();
     gather_sorted(P, alpha, xs);
     posterior_sorted(P, xs, m, targets, sigma_t, l_t, mu);
     return GP_OK;
+  });
+}
+
+__global__ void unit_vector_kernel(int64_t m, int64_t pos, double* e) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) e[i] = i == pos ? 1.0 : 0.0;
+}
+
+// column j of the covariance from sorted-order prior and cross terms
+__global__ void cov_column_kernel(int64_t m, const int* __restrict__ perm,
+                                  const double* __restrict__ prior, const double* __restrict__ cross,
+                                  int64_t j, double* __restrict__ cov, double* __restrict__ var) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= m) return;
+  const int64_t i = perm[s];
+  const double c = prior[s] - cross[s];
+  if (cov) cov[i * m + j] = c;
+  if (var && i == j) var[j] = c;
+}
+
+int gp_posterior_cov(gp_plan_t h, int64_t m, const double* targets, const double* sigma_t,
+                     const double* l_t, double tol, int max_iter, double* cov, double* var,
+                     gp_cg_info* info) {
+  return guarded([&] {
+    if (!h || !targets || !sigma_t || !l_t || (!cov && !var)) throw Error{GP_EINVAL, "null argument"};
+    if (m < 1) throw Error{GP_EINVAL, "m must be >= 1"};
+    if (!(tol > 0) || max_iter < 1) throw Error{GP_EINVAL, "tol must be > 0 and max_iter >= 1"};
+    Plan* P = &h->P;
+    validate_targets(P, m, targets, sigma_t, l_t);
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = P->stream;
+    Records T;
+    int oob = 0;
+    build_records_into(P, m, targets, sigma_t, l_t, T, &oob);
+    if (oob) throw Error{GP_ERANGE, "target outside the plan's box"};
+    std::vector<int> perm(m), inv(m);
+    GP_HIP(hipMemcpyAsync(perm.data(), T.perm.p, m * sizeof(int), hipMemcpyDeviceToHost, s));
+    GP_HIP(hipStreamSynchronize(s));
+    for (int64_t q = 0; q < m; ++q) inv[perm[q]] = (int)q;
+    const int64_t n = P->n;
+    DevBuf e, prior, cross, kb, vb;
+    e.alloc(m * sizeof(double));
+    prior.alloc(m * sizeof(double));
+    cross.alloc(m * sizeof(double));
+    kb.alloc(n * sizeof(double));
+    vb.alloc(n * sizeof(double));
+    const unsigned mb = (unsigned)((m + 255) / 256);
+    int64_t total = 0;
+    double worst = 0.0;
+    int status = GP_OK;
+    for (int64_t j = 0; j < m; ++j) {
+      // k_j = K~(X, x*_j) and the prior column K~(X*, x*_j) from one forward pass
+      hipLaunchKernelGGL(unit_vector_kernel, dim3(mb), dim3(256), 0, s, m, (int64_t)inv[j],
+                         e.as<double>());
+      GP_CHECK_LAUNCH();
+      forward_from(P, T, e.as<double>());
+      interp_from_grid(P, P->rec, kb.as<double>());
+      interp_from_grid(P, T, prior.as<double>());
+      // v_j = (K~ + eta^2 I)^{-1} k_j
+      GP_HIP(hipMemsetAsync(vb.p, 0, n * sizeof(double), s));
+      int it = 0;
+      double rel = 0.0;
+      const int st = cg_solve_sorted(P, kb.as<double>(), vb.as<double>(), true, tol, max_iter, 0,
+                                     &it, &rel);
+      total += it;
+      worst = std::max(worst, rel);
+      if (st != GP_OK) status = st;
+      // cross term K~(X*, X) v_j
+      forward_from(P, P->rec, vb.as<double>());
+      interp_from_grid(P, T, cross.as<double>());
+      hipLaunchKernelGGL(cov_column_kernel, dim3(mb), dim3(256), 0, s, m, T.perm.as<int>(),
+                         prior.as<double>(), cross.as<double>(), j, cov, var);
+      GP_CHECK_LAUNCH();
+    }
+    GP_HIP(hipStreamSynchronize(s));
+    if (info) {
+      info->iters = (int)std::min<int64_t>(total, INT32_MAX);
+      info->status = status;
+      info->rel_res = worst;
+      info->rel_res_true = -1.0;
+      info->refinements = 0;
+      info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (status != GP_OK) set_error("a CG solve reached max_iter before the tolerance");
+    return status;
   });
 }
 

@@ -85,8 +85,11 @@ struct Records {
   //  sp_red   int4 {tile, slot0, count, 0}: grid tile = sum of its partials,
   //           added in slot order
   //  in_work  int4 {bin, p_lo, p_hi, 0}: interpolate sorted points [p_lo, p_hi)
-  DevBuf sp_work, sp_red, in_work, part;
-  int64_t n_sp_work = 0, n_sp_red = 0, n_in_work = 0, n_slots = 0;
+  //  in_work2 int4 {super-bin, lo, hi, 0} (d = 2): interpolate positions
+  //           [lo, hi) of the points of a 2x2 block of bins (its two bin rows
+  //           in order, each a contiguous range of the sorted points)
+  DevBuf sp_work, sp_red, in_work, in_work2, part;
+  int64_t n_sp_work = 0, n_sp_red = 0, n_in_work = 0, n_in_work2 = 0, n_slots = 0;
 };
 
 // ------------------------------------------------------------------- plan --
@@ -139,7 +142,7 @@ struct Plan {
   DevBuf vtd;                 // T [nt] v~_j
   int step3 = 0;              // 0: radial precomputed A, 1: direct t-sum
   int spread_owner = 1;       // 1: owner-computes spreading (no atomics), 0: LDS-atomic items
-  int interp_gather = 0;      // 1: one thread per point from cache, 0: LDS-staged tiles
+  int interp_mode = 0;        // 0 default, 1 cache gather, 2 per-bin LDS tiles
   int64_t a_rows = 0;         // distinct |n|^2 values (rows of A)
   int nkp = 0;                // table width: nk rounded up to even
   DevBuf atab;                // T [a_rows][nkp(nkp+1)/2] upper triangle of A_k'k(|n|^2)
@@ -193,6 +196,14 @@ void matvec_sorted(Plan* P, const double* x_sorted, double* y_sorted, int add_no
 void posterior_sorted(Plan* P, const double* x_sorted, int64_t m, const double* tpts,
                       const double* tsig, const double* tl, double* mu);
 // gather / scatter between caller and sorted order
+// K~ between record sets of one plan (same grid and box): forward_from puts
+// the grids of sum_i xs_i delta(x - x_i) over the points of R (sorted order)
+// through spreading, both FFTs and the mode mixing; interp_from_grid then
+// writes ys = K~(points of R', those points) xs for any record set R'.
+void forward_from(Plan* P, const Records& R, const double* xs);
+void interp_from_grid(Plan* P, const Records& R, double* ys);
+void build_records_into(Plan* P, int64_t n, const double* pts, const double* sig,
+                        const double* l, Records& R, int* out_of_box);
 void gather_sorted(Plan* P, const double* x_user, double* x_sorted);
 void scatter_user(Plan* P, const double* x_sorted, double* x_user);
 

@@ -26,8 +26,6 @@
 
 namespace gp {
 
-void build_records_into(Plan* P, int64_t n, const double* pts, const double* sig,
-                        const double* l, Records& R, int* out_of_box);
 void mix_modes_fp64(Plan* P);
 void mix_modes_fp32(Plan* P);
 static void mix_modes(Plan* P) {
@@ -521,6 +519,117 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(
   }
 }
 
+// ------------------------------------------------- interp (2x2 super-tile) ----
+// d = 2.  One workgroup per chunk of the points of a 2x2 block of bins: the
+// block's cells plus the (w-1) halo are staged in LDS for one grid pair at a
+// time (halo overhead (2t+w-1)^2/(2t)^2 instead of (t+w-1)^2/t^2 per bin), the
+// points' rows are staged once, and each thread keeps its items' partial sums
+// over all pairs in registers.  Items are (row group, point), row group
+// fastest; the RG lanes of a point combine by xor shuffles at the end, so the
+// order of every sum is fixed.
+constexpr int kPB2 = 128;                                   // points staged per batch
+constexpr int kNI2 = (kPB2 * kRG + kThreads - 1) / kThreads;  // items per thread
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void interp_super_kernel(
+    NuArgs a, const typename V2<T>::type* __restrict__ grid, const int* __restrict__ cell,
+    const T* __restrict__ pw, int rs, const int* __restrict__ bin_start,
+    const int4* __restrict__ work, const double* __restrict__ x, double* __restrict__ y) {
+  using V = typename V2<T>::type;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int w = a.w;
+  const int st0 = 2 * a.tile[0], st1 = 2 * a.tile[1];
+  const int pc0 = st0 + w - 1, pc1 = st1 + w - 1;
+  const int ps0 = pc0 | 1;  // odd row stride: the RG lanes of a point hit different banks
+  const int ls = lds_stride(rs);
+  V* tile = reinterpret_cast<V*>(smem);                          // [pc1][ps0]
+  T* s_rec = reinterpret_cast<T*>(tile + (size_t)ps0 * pc1);     // [kPB2][ls]
+  int* s_cell = reinterpret_cast<int*>(s_rec + kPB2 * ls);       // [kPB2][2]
+  int* s_idx = s_cell + 2 * kPB2;                                 // [kPB2] sorted index
+
+  const int4 wk = work[blockIdx.x];
+  const int nsb0 = (a.nbins[0] + 1) / 2;
+  const int sx = wk.x % nsb0, sy = wk.x / nsb0;
+  const int t00 = sx * st0, t01 = sy * st1;
+  const int bx0 = 2 * sx, bx1 = min(2 * sx + 1, a.nbins[0] - 1);
+  int r_lo[2] = {0, 0}, r_len0 = 0;
+  for (int q = 0; q < 2; ++q) {
+    const int by = 2 * sy + q;
+    if (by >= a.nbins[1]) break;
+    r_lo[q] = bin_start[by * a.nbins[0] + bx0];
+    if (q == 0) r_len0 = bin_start[by * a.nbins[0] + bx1 + 1] - r_lo[0];
+  }
+  const int RG = w >= kRG ? kRG : (w >= 2 ? 2 : 1);  // power of two; kThreads % RG == 0
+  const int wko = 2 * w;
+  for (int pos = wk.y; pos < wk.z; pos += kPB2) {
+    const int np = min(kPB2, wk.z - pos);
+    __syncthreads();
+    for (int e = threadIdx.x; e < np; e += kThreads) {
+      const int q = pos + e;
+      const int idx = q < r_len0 ? r_lo[0] + q : r_lo[1] + (q - r_len0);
+      s_idx[e] = idx;
+      s_cell[2 * e] = cell[idx] - t00;
+      s_cell[2 * e + 1] = cell[a.n + idx] - t01;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < np * rs; e += kThreads) {
+      const int p = e / rs, c = e - p * rs;
+      s_rec[p * ls + c] = pw[(int64_t)s_idx[p] * rs + c];
+    }
+    double part[kNI2];
+#pragma unroll
+    for (int k = 0; k < kNI2; ++k) part[k] = 0.0;
+    const int nitems = np * RG;
+    for (int g = 0; g < a.npair; ++g) {
+      __syncthreads();  // records staged / previous pair's tile no longer read
+      for (int e = threadIdx.x; e < pc0 * pc1; e += kThreads) {
+        const int l1 = e / pc0, l0 = e - l1 * pc0;
+        const int c0 = t00 + l0, c1 = t01 + l1;
+        V v = V{T(0), T(0)};
+        if (c0 < a.na[0] && c1 < a.na[1])
+          v = grid[(int64_t)g * a.pair_stride + a.grid_off + (int64_t)c0 * a.gstride[0] +
+                   (int64_t)c1 * a.gstride[1]];
+        tile[l1 * ps0 + l0] = v;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < kNI2; ++k) {
+        const int it = threadIdx.x + k * kThreads;
+        if (it < nitems) {
+          const int rg = it % RG, p = it / RG;
+          const T* pr = s_rec + p * ls;
+          const int o0 = s_cell[2 * p], o1 = s_cell[2 * p + 1];
+          double acc = 0.0;
+          for (int row = rg; row < w; row += RG) {
+            const V* tr = tile + (o1 + row) * ps0 + o0;
+            T rx = 0, ry = 0;
+            for (int q0 = 0; q0 < w; ++q0) {
+              const T ps = pr[q0];
+              const V gv = tr[q0];
+              rx += ps * gv.x;
+              ry += ps * gv.y;
+            }
+            acc += (double)pr[w + row] * ((double)pr[wko + 2 * g] * (double)rx +
+                                          (double)pr[wko + 2 * g + 1] * (double)ry);
+          }
+          part[k] += acc;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kNI2; ++k) {
+      const int it = threadIdx.x + k * kThreads;  // a lane group is all in or all out
+      double v = part[k];
+      if (RG >= 2) v += __shfl_xor(v, 1);
+      if (RG >= 4) v += __shfl_xor(v, 2);
+      if (it < nitems && it % RG == 0) {
+        const int i = s_idx[it / RG];
+        y[i] = (a.add_noise ? a.eta2 * x[i] : 0.0) + v;
+      }
+    }
+  }
+}
+
 __global__ void gather_kernel(int64_t n, const int* __restrict__ perm, const double* __restrict__ u,
                               double* __restrict__ s) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -549,9 +658,10 @@ size_t interp_smem(const Plan* P, int gc, int rs) {
 
 constexpr size_t kSmemCap = 64 * 1024;
 
-NuArgs nu_args(const Plan* P) {
+// Kernel arguments for the point set R (training points or targets) of plan P.
+NuArgs nu_args(const Plan* P, const Records& R) {
   NuArgs a;
-  a.n = P->n;
+  a.n = R.n;
   a.nk = P->nk;
   a.npair = P->npair;
   a.w = P->w;
@@ -586,10 +696,9 @@ size_t spread_owner_smem(const Plan* P, int rs) {
 }
 
 template <typename T, int D, int CPT>
-void launch_spread_owner(Plan* P, const double* xs) {
+void launch_spread_owner(Plan* P, const Records& R, const double* xs) {
   PhaseScope ps(P, PH_SPREAD);
-  NuArgs a = nu_args(P);
-  const Records& R = P->rec;
+  NuArgs a = nu_args(P, R);
   const int gc = std::min(kGC, P->npair);
   const int nch = (P->npair + gc - 1) / gc;
   for (int ch = 0; ch < nch; ++ch) {
@@ -612,10 +721,9 @@ void launch_spread_owner(Plan* P, const double* xs) {
 }
 
 template <typename T, int D>
-void launch_spread(Plan* P, const double* xs) {
+void launch_spread(Plan* P, const Records& R, const double* xs) {
   PhaseScope ps(P, PH_SPREAD);
-  NuArgs a = nu_args(P);
-  const Records& R = P->rec;
+  NuArgs a = nu_args(P, R);
   int gc = std::min(kGC, P->npair);
   while (gc > 1 && spread_smem<T>(P, gc, R.rs) > kSmemCap) --gc;
   const int nch = (P->npair + gc - 1) / gc;
@@ -644,8 +752,7 @@ void allow_big_lds(K kernel) {
 template <typename T, int D>
 void launch_interp(Plan* P, const Records& R, const double* xs, double* ys, int add_noise) {
   PhaseScope ps(P, PH_INTERP);
-  NuArgs a = nu_args(P);
-  a.n = R.n;
+  NuArgs a = nu_args(P, R);
   a.add_noise = add_noise;
   allow_big_lds(interp_kernel<T, D>);
   int gc = std::min(kGC, P->npair);
@@ -667,25 +774,24 @@ void launch_interp(Plan* P, const Records& R, const double* xs, double* ys, int 
 }
 
 template <typename T>
-void spread_dispatch(Plan* P, const double* xs) {
+void spread_dispatch(Plan* P, const Records& R, const double* xs) {
   const int tcells = P->tile[0] * P->tile[1] * P->tile[2];
   if (P->spread_owner && tcells <= 2 * kThreads) {
     const bool two = tcells > kThreads;
-    if (P->d == 1) two ? launch_spread_owner<T, 1, 2>(P, xs) : launch_spread_owner<T, 1, 1>(P, xs);
-    else if (P->d == 2) two ? launch_spread_owner<T, 2, 2>(P, xs) : launch_spread_owner<T, 2, 1>(P, xs);
-    else two ? launch_spread_owner<T, 3, 2>(P, xs) : launch_spread_owner<T, 3, 1>(P, xs);
+    if (P->d == 1) two ? launch_spread_owner<T, 1, 2>(P, R, xs) : launch_spread_owner<T, 1, 1>(P, R, xs);
+    else if (P->d == 2) two ? launch_spread_owner<T, 2, 2>(P, R, xs) : launch_spread_owner<T, 2, 1>(P, R, xs);
+    else two ? launch_spread_owner<T, 3, 2>(P, R, xs) : launch_spread_owner<T, 3, 1>(P, R, xs);
     return;
   }
-  if (P->d == 1) launch_spread<T, 1>(P, xs);
-  else if (P->d == 2) launch_spread<T, 2>(P, xs);
-  else launch_spread<T, 3>(P, xs);
+  if (P->d == 1) launch_spread<T, 1>(P, R, xs);
+  else if (P->d == 2) launch_spread<T, 2>(P, R, xs);
+  else launch_spread<T, 3>(P, R, xs);
 }
 
 template <typename T, int D, int WT>
 void launch_interp_gather(Plan* P, const Records& R, const double* xs, double* ys, int add_noise) {
   PhaseScope ps(P, PH_INTERP);
-  NuArgs a = nu_args(P);
-  a.n = R.n;
+  NuArgs a = nu_args(P, R);
   a.add_noise = add_noise;
   const DevBuf& g = P->fourstep ? P->gridC : P->gridA;
   hipLaunchKernelGGL((interp_gather_kernel<T, D, WT>), dim3((unsigned)((R.n + kThreads - 1) / kThreads)),
@@ -695,8 +801,32 @@ void launch_interp_gather(Plan* P, const Records& R, const double* xs, double* y
 }
 
 template <typename T>
+size_t interp_super_smem(const Plan* P, int rs) {
+  const size_t pc0 = (size_t)(2 * P->tile[0] + P->w - 1), pc1 = (size_t)(2 * P->tile[1] + P->w - 1);
+  return (pc0 | 1) * pc1 * sizeof(typename V2<T>::type) + (size_t)kPB2 * lds_stride(rs) * sizeof(T) +
+         3 * kPB2 * sizeof(int) + 16;
+}
+
+template <typename T>
+void launch_interp_super(Plan* P, const Records& R, const double* xs, double* ys, int add_noise) {
+  PhaseScope ps(P, PH_INTERP);
+  NuArgs a = nu_args(P, R);
+  a.add_noise = add_noise;
+  if (R.n_in_work2 == 0) return;
+  hipLaunchKernelGGL((interp_super_kernel<T>), dim3((unsigned)R.n_in_work2), dim3(kThreads),
+                     interp_super_smem<T>(P, R.rs), P->stream, a,
+                     P->gridA.as<typename V2<T>::type>(), R.cell.as<int>(), R.pw.as<T>(), R.rs,
+                     R.bin_start.as<int>(), R.in_work2.as<int4>(), xs, ys);
+  GP_CHECK_LAUNCH();
+}
+
+template <typename T>
 void interp_dispatch(Plan* P, const Records& R, const double* xs, double* ys, int add_noise) {
-  if (P->interp_gather) {  // cache-gather variant
+  if (P->interp_mode == 0 && P->d == 2 && interp_super_smem<T>(P, R.rs) <= kSmemCap) {
+    launch_interp_super<T>(P, R, xs, ys, add_noise);
+    return;
+  }
+  if (P->interp_mode == 1) {  // cache-gather variant
     const bool big = P->w > 8;
 #define GP_IG(DD) big ? launch_interp_gather<T, DD, 16>(P, R, xs, ys, add_noise) \
                       : launch_interp_gather<T, DD, 8>(P, R, xs, ys, add_noise)
@@ -808,8 +938,8 @@ void fft_all(Plan* P, int sign) {
 }
 
 template <typename T>
-void forward_and_mix(Plan* P, const double* xs) {
-  spread_dispatch<T>(P, xs);
+void forward_and_mix(Plan* P, const Records& R, const double* xs) {
+  spread_dispatch<T>(P, R, xs);
   fft_all(P, -1);
   mix_modes(P);
   fft_all(P, +1);
@@ -819,10 +949,10 @@ void forward_and_mix(Plan* P, const double* xs) {
 
 void matvec_sorted(Plan* P, const double* xs, double* ys, int add_noise) {
   if (P->precision == GP_FP64) {
-    forward_and_mix<double>(P, xs);
+    forward_and_mix<double>(P, P->rec, xs);
     interp_dispatch<double>(P, P->rec, xs, ys, add_noise);
   } else {
-    forward_and_mix<float>(P, xs);
+    forward_and_mix<float>(P, P->rec, xs);
     interp_dispatch<float>(P, P->rec, xs, ys, add_noise);
   }
 }
@@ -836,16 +966,32 @@ void posterior_sorted(Plan* P, const double* xs, int64_t m, const double* tpts,
   DevBuf tmp;
   tmp.alloc(m * sizeof(double));
   if (P->precision == GP_FP64) {
-    forward_and_mix<double>(P, xs);
+    forward_and_mix<double>(P, P->rec, xs);
     interp_dispatch<double>(P, T, nullptr, tmp.as<double>(), 0);
   } else {
-    forward_and_mix<float>(P, xs);
+    forward_and_mix<float>(P, P->rec, xs);
     interp_dispatch<float>(P, T, nullptr, tmp.as<double>(), 0);
   }
   hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, P->stream,
                      m, T.perm.as<int>(), tmp.as<double>(), mu);
   GP_CHECK_LAUNCH();
   GP_HIP(hipStreamSynchronize(P->stream));
+}
+
+// Grids for the points of R weighted by xs (sorted order of R): spread,
+// forward FFT, mode mixing, inverse FFT.  interp_from_grid then evaluates the
+// result at the points of another record set of the same plan.
+void forward_from(Plan* P, const Records& R, const double* xs) {
+  if (P->precision == GP_FP64)
+    forward_and_mix<double>(P, R, xs);
+  else
+    forward_and_mix<float>(P, R, xs);
+}
+void interp_from_grid(Plan* P, const Records& R, double* ys) {
+  if (P->precision == GP_FP64)
+    interp_dispatch<double>(P, R, nullptr, ys, 0);
+  else
+    interp_dispatch<float>(P, R, nullptr, ys, 0);
 }
 
 void gather_sorted(Plan* P, const double* xu, double* xs) {

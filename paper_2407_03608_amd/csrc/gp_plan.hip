@@ -319,7 +319,8 @@ size_t work_list_bound_bytes(const Plan* P, int64_t n, size_t cs) {
   const int64_t items = P->n_bins + ts / qs + 1;
   const int64_t qi = std::max(kMinInterpChunk, n / kTargetItems);
   const int64_t iitems = P->n_bins + n / qi + 1;
-  return (size_t)(2 * items + iitems) * 16 + (size_t)slots * tcells * kSlotPairs * cs;
+  const int64_t sitems = P->d == 2 ? P->n_bins / 4 + 2 * P->nbins[0] + n / 128 + 1 : 0;
+  return (size_t)(2 * items + iitems + sitems) * 16 + (size_t)slots * tcells * kSlotPairs * cs;
 }
 
 // Build the spread and interpolation work lists from the bin offsets.  The
@@ -381,7 +382,34 @@ static void build_work_lists(Plan* P, Records& R, const std::vector<int>& start,
     for (int64_t j = 0; j < c; ++j)
       inw.insert(inw.end(), {(int)b, (int)(start[b] + cnt * j / c), (int)(start[b] + cnt * (j + 1) / c), 0});
   }
+  // 2x2 super-bins (d = 2): the points of bin rows 2sy and 2sy+1, bins
+  // 2sx..2sx+1 of each, in that order
+  const int64_t kSuperChunkMin = 128;
+  std::vector<int> inw2;
+  if (d == 2) {
+    const int64_t q2 = std::max(kSuperChunkMin, R.n / kTargetItems);
+    const int nsb0 = (P->nbins[0] + 1) / 2, nsb1 = (P->nbins[1] + 1) / 2;
+    for (int sy = 0; sy < nsb1; ++sy)
+      for (int sx = 0; sx < nsb0; ++sx) {
+        const int bx0 = 2 * sx, bx1 = std::min(2 * sx + 1, P->nbins[0] - 1);
+        int64_t cnt = 0;
+        for (int q = 0; q < 2; ++q) {
+          const int by = 2 * sy + q;
+          if (by >= P->nbins[1]) break;
+          cnt += start[(int64_t)by * P->nbins[0] + bx1 + 1] - start[(int64_t)by * P->nbins[0] + bx0];
+        }
+        if (cnt == 0) continue;
+        const int64_t c = (cnt + q2 - 1) / q2;
+        for (int64_t j = 0; j < c; ++j)
+          inw2.insert(inw2.end(), {sy * nsb0 + sx, (int)(cnt * j / c), (int)(cnt * (j + 1) / c), 0});
+      }
+  }
   hipStream_t s = P->stream;
+  R.n_in_work2 = (int64_t)inw2.size() / 4;
+  if (!inw2.empty()) {
+    R.in_work2.alloc(inw2.size() * sizeof(int));
+    GP_HIP(hipMemcpyAsync(R.in_work2.p, inw2.data(), inw2.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  }
   R.n_sp_work = (int64_t)spw.size() / 4;
   R.n_sp_red = (int64_t)spr.size() / 4;
   R.n_in_work = (int64_t)inw.size() / 4;
@@ -713,7 +741,8 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
   // ---- step 3 variant; radial rows of the precomputed tensor
   P->step3 = opts.step3 ? 1 : 0;
   P->spread_owner = opts.spread ? 0 : 1;
-  P->interp_gather = opts.interp ? 1 : 0;
+  if (opts.interp < 0 || opts.interp > 2) throw Error{GP_EINVAL, "opts.interp must be 0, 1 or 2"};
+  P->interp_mode = opts.interp;
   P->nkp = P->nk + (P->nk & 1);
   std::vector<double> svals;
   std::vector<int> rowmap;

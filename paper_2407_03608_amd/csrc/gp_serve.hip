@@ -2,11 +2,11 @@
 //
 // Each request is one solve of (K~ + eta^2 I) alpha = y (eq:gprsolve) on its own
 // points and hyperparameters.  The server owns `max_slots` worker threads,
-// each with its own non-blocking HIP stream.  A request is admitted in arrival
-// order as soon as a slot is free and the device bytes of its plans fit in the
-// budget next to the requests already in flight; its plan(s) are built, the
-// solve runs on the slot's stream (so requests overlap on the device), alpha
-// is written to the caller's buffer and the plans are released.
+// each with its own non-blocking HIP stream.  A free slot admits a queued
+// request whose plans fit in the device-byte budget next to the requests
+// already in flight (oldest first, or smallest first with aging); its plan(s)
+// are built, the solve runs on the slot's stream (so requests overlap on the
+// device), alpha is written to the caller's buffer and the plans are released.
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -112,6 +112,26 @@ void run_request(Server& S, SRequest& r, hipStream_t st) {
   r.refinements = passes;
 }
 
+// Queued request to admit next (queue.end() if none may start now); called
+// with the lock held.
+std::deque<SRequest*>::iterator pick_next(Server* S) {
+  auto best = S->queue.end();
+  double best_key = 0.0;
+  const double now = S->now();
+  for (auto it = S->queue.begin(); it != S->queue.end(); ++it) {
+    const SRequest* r = *it;
+    const bool fits = S->bytes_in_use + r->bytes <= S->o.max_device_bytes || S->running == 0;
+    if (S->o.policy == GP_SERVE_FIFO) return fits ? it : S->queue.end();
+    if (!fits) continue;
+    const double key = (double)r->bytes - S->o.aging_bytes_per_s * (now - r->t_submit);
+    if (best == S->queue.end() || key < best_key) {
+      best = it;
+      best_key = key;
+    }
+  }
+  return best;
+}
+
 void worker(Server* S, int slot) {
   hipStream_t st = S->streams[slot];
   while (true) {
@@ -120,13 +140,13 @@ void worker(Server* S, int slot) {
       std::unique_lock<std::mutex> lk(S->mu);
       S->cv_work.wait(lk, [&] {
         if (S->stop && S->queue.empty()) return true;
-        if (S->queue.empty()) return false;
-        return S->bytes_in_use + S->queue.front()->bytes <= S->o.max_device_bytes ||
-               S->running == 0;
+        return pick_next(S) != S->queue.end();
       });
       if (S->queue.empty()) return;  // stop requested and nothing left
-      r = S->queue.front();
-      S->queue.pop_front();
+      auto it = pick_next(S);
+      if (it == S->queue.end()) continue;
+      r = *it;
+      S->queue.erase(it);
       S->bytes_in_use += r->bytes;
       S->peak_bytes = std::max(S->peak_bytes, S->bytes_in_use);
       S->running += 1;
@@ -194,6 +214,8 @@ int gp_server_opts_init(gp_server_opts* o) {
   o->max_iter = 20000;
   o->max_refine = 10;
   o->fp64_below_bytes = (size_t)256 << 20;
+  o->policy = GP_SERVE_SMALLEST;
+  o->aging_bytes_per_s = (double)((size_t)1 << 30);
   return GP_OK;
 }
 
@@ -203,6 +225,9 @@ int gp_server_create(const gp_server_opts* opts, gp_server_t* out) {
     if (opts->max_slots < 1 || opts->max_slots > 64) throw Error{GP_EINVAL, "max_slots in 1..64"};
     if (opts->precision != GP_FP64 && opts->precision != GP_FP32_BULK)
       throw Error{GP_EINVAL, "unknown precision"};
+    if (opts->policy != GP_SERVE_FIFO && opts->policy != GP_SERVE_SMALLEST)
+      throw Error{GP_EINVAL, "unknown admission policy"};
+    if (!(opts->aging_bytes_per_s >= 0)) throw Error{GP_EINVAL, "aging_bytes_per_s must be >= 0"};
     auto* h = new gp_server_s();
     Server& S = h->S;
     S.o = *opts;

@@ -25,6 +25,8 @@ GP_EDEVICE = -6
 GP_EUNSUPPORTED = -7
 GP_FP64 = 0
 GP_FP32_BULK = 1
+GP_SERVE_FIFO = 0
+GP_SERVE_SMALLEST = 1
 
 _c_d = ctypes.c_double
 _c_i = ctypes.c_int
@@ -118,6 +120,7 @@ EXPORTS = [
     "gp_plan_destroy",
     "gp_last_error",
     "gp_residual",
+    "gp_posterior_cov",
     "gp_plan_set_timing",
     "gp_plan_get_timing",
     "gp_server_opts_init",
@@ -142,6 +145,8 @@ class GpServerOpts(ctypes.Structure):
         ("max_iter", _c_i),
         ("max_refine", _c_i),
         ("fp64_below_bytes", _c_sz),
+        ("policy", _c_i),
+        ("aging_bytes_per_s", _c_d),
     ]
 
 
@@ -225,6 +230,9 @@ def load(path: str = LIB_PATH):
     L.gp_residual.restype = _c_i
     L.gp_plan_set_timing.argtypes = [_c_p, _c_i]
     L.gp_plan_set_timing.restype = _c_i
+    L.gp_posterior_cov.argtypes = [_c_p, _c_i64, _c_p, _c_p, _c_p, _c_d, _c_i, _c_p, _c_p,
+                                   ctypes.POINTER(GpCgInfo)]
+    L.gp_posterior_cov.restype = _c_i
     L.gp_plan_get_timing.argtypes = [_c_p, ctypes.POINTER(GpTiming)]
     L.gp_plan_get_timing.restype = _c_i
     L.gp_server_opts_init.argtypes = [ctypes.POINTER(GpServerOpts)]
@@ -347,6 +355,26 @@ class Plan:
                                         targets.data_ptr(), sigma_t.data_ptr(), l_t.data_ptr(),
                                         mu.data_ptr()))
         return mu
+
+    def posterior_cov(self, targets: torch.Tensor, sigma_t: torch.Tensor, l_t: torch.Tensor,
+                      tol: float = 1e-8, max_iter: int = 10000, full: bool = True):
+        """(cov m x m or None, var m, info) of eq:postcov at the targets."""
+        targets = _dev(targets, "targets")
+        if targets.dim() == 1:
+            targets = targets[:, None].contiguous()
+        sigma_t = _dev(sigma_t, "sigma_t")
+        l_t = _dev(l_t, "l_t")
+        m = targets.shape[0]
+        var = torch.empty(m, dtype=torch.float64, device=targets.device)
+        cov = torch.empty((m, m), dtype=torch.float64, device=targets.device) if full else None
+        info = GpCgInfo()
+        rc = load().gp_posterior_cov(self._h, m, targets.data_ptr(), sigma_t.data_ptr(),
+                                     l_t.data_ptr(), float(tol), int(max_iter),
+                                     cov.data_ptr() if full else None, var.data_ptr(),
+                                     ctypes.byref(info))
+        if rc not in (GP_OK, GP_ENOCONV):
+            _check(rc)
+        return cov, var, _info_dict(info)
 
     def residual(self, y: torch.Tensor, alpha: torch.Tensor) -> float:
         """||y - (K~ + eta^2 I) alpha|| / ||y|| with this plan's operator."""

@@ -78,14 +78,15 @@ def test_step3_variants_agree(gp, d, M, prec):
 
 @pytest.mark.parametrize("d,M,prec", [(1, 150, 0), (2, 24, 0), (3, 8, 0), (2, 24, 1), (3, 8, 1)])
 def test_spread_and_interp_variants(gp, d, M, prec):
-    """Owner-computes / LDS-atomic spreading and cache-gather / LDS-tile
-    interpolation realise the same operator (each checked against the oracle)."""
+    """Owner-computes / LDS-atomic spreading and super-tile (default in d=2) /
+    cache-gather / per-bin-tile interpolation realise the same operator (each
+    checked against the oracle)."""
     prob = inputs.random_small(d, 700 if d < 3 else 400, seed=60 + d, nu=1.5, lmin=0.08, lmax=0.2)
     tol = 1e-9 if prec == 0 else 1e-4
     bar = FP64_TOL if prec == 0 else FP32_TOL
     outs = []
     for sp in (0, 1):
-        for ip in (0, 1):
+        for ip in (0, 1, 2):
             P, info, a, got, ref = _check_matvec(gp, prob, tol=tol, precision=prec, bar=bar, M=M,
                                                  spread=sp, interp=ip)
             assert info["spread"] == sp and info["interp"] == ip
@@ -272,6 +273,34 @@ def test_posterior_mean(gp):
     mu = host(P.posterior_mean(al, cuda(xt), cuda(st), cuda(lt)))
     Kt = O.ktilde_entries(oracle_params(P.info()), xt, st, lt, prob.x, prob.sigma, prob.l)
     assert rel(mu, Kt @ alh) < FP64_TOL
+
+
+@pytest.mark.parametrize("d", [1, 2])
+def test_posterior_cov_vs_oracle(gp, d):
+    """eq:postcov: GPU covariance (one CG solve per target) against the oracle's
+    Schur complement of K~ entries (Cholesky), same plan parameters."""
+    n = 200 if d == 1 else 120
+    prob = inputs.random_small(d, n, seed=50 + d, nu=1.5, lmin=0.12, lmax=0.2, eta=0.3)
+    P = _plan(gp, prob, tol=1e-6, nufft_tol=1e-11, M=60 if d == 1 else 14)
+    info = P.info()
+    rng = np.random.default_rng(5)
+    m = 6
+    xt = rng.uniform(prob.x.min(0), prob.x.max(0), size=(m, d))
+    lt = rng.uniform(prob.l.min(), prob.l.max(), size=m)
+    st = rng.uniform(0.7, 1.3, size=m)
+    cov, var, ci = P.posterior_cov(cuda(xt), cuda(st), cuda(lt), tol=1e-12, max_iter=5000)
+    say(f"  cov solves: {ci}")
+    assert ci["status"] == 0
+    ref = O.ktilde_posterior_cov(oracle_params(info), prob.x, prob.sigma, prob.l, prob.eta, xt, st, lt)
+    c = host(cov)
+    e = float(np.linalg.norm(c - ref) / np.linalg.norm(ref))
+    say(f"  covariance rel err vs oracle = {e:.3e}")
+    assert e <= FP64_TOL
+    assert np.array_equal(host(var), np.diag(c))
+    assert np.all(host(var) > 0) and np.all(host(var) < st ** 2)
+    # variances alone: same values
+    none, var2, _ = P.posterior_cov(cuda(xt), cuda(st), cuda(lt), tol=1e-12, max_iter=5000, full=False)
+    assert none is None and np.array_equal(host(var2), host(var))
 
 
 def test_errors_are_reported(gp):

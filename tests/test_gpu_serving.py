@@ -45,7 +45,7 @@ def _requests(k):
 
 
 def test_server_alone_vs_mix(gp):
-    probs = _requests(12)
+    probs = _requests(16)
     dev = [(cuda(p.x), cuda(p.sigma), cuda(p.l), cuda(p.y)) for p in probs]
     # alone: one slot, one request at a time
     S1 = gp.Server(max_slots=1, max_iter=6000)
@@ -56,8 +56,8 @@ def test_server_alone_vs_mix(gp):
         say(f"  alone req d={p.d} n={p.n} nu={p.nu} iters={info['iters']} rel={info['rel_res']:.2e} status={info['status']}")
         alone.append((host(a), info))
     S1.close()
-    # mix: everything submitted at once to a 6-slot server
-    S6 = gp.Server(max_slots=6, max_iter=6000)
+    # mix: everything submitted at once to a 6-slot server (smallest-first admission)
+    S6 = gp.Server(max_slots=6, max_iter=6000, policy=gp.GP_SERVE_SMALLEST)
     ids = [S6.submit(x, s, l, p.nu, p.eta, y) for p, (x, s, l, y) in zip(probs, dev)]
     mix = [S6.wait(i) for i in ids]
     st = S6.stats()

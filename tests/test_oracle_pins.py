@@ -315,3 +315,60 @@ def test_ktilde_stationary_se_matches_textbook_kernel():
     Kt = O.ktilde_entries(p, prob.x, s, l)
     r2 = ((prob.x[:, None] - prob.x[None]) ** 2).sum(-1)
     assert np.abs(Kt - 0.64 * np.exp(-r2 / (2 * 0.22 ** 2))).max() < 1e-10
+
+
+# ------------------------------------------------- posterior covariance ----
+
+def test_posterior_cov_single_training_point_closed_form():
+    """eq:postcov with one observation: Sigma(a, b) = k(a, b) - k(a, x1) k(x1, b) / (k(x1, x1) + eta^2)."""
+    rng = np.random.default_rng(31)
+    x = rng.uniform(0, 1, (1, 2))
+    sx, lx = np.array([1.3]), np.array([0.2])
+    xt = rng.uniform(0, 1, (4, 2))
+    st, lt = rng.uniform(0.8, 1.2, 4), rng.uniform(0.1, 0.3, 4)
+    eta = 0.3
+    got = O.posterior_cov_exact(x, sx, lx, 1.5, eta, xt, st, lt)
+    kab = O.kernel_matrix(xt, st, lt, 1.5)
+    ka1 = O.kernel_matrix(xt, st, lt, 1.5, x, sx, lx)[:, 0]
+    ref = kab - np.outer(ka1, ka1) / (sx[0] ** 2 + eta ** 2)
+    assert np.allclose(got, ref, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("nu", [0.5, 2.5])
+def test_posterior_cov_at_training_points_noise_identity(nu):
+    """At the training points eq:postcov equals eta^2 K (K + eta^2 I)^{-1}."""
+    prob = inputs.random_small(2, 60, seed=32, nu=nu, eta=0.2)
+    C = O.posterior_cov_exact(prob.x, prob.sigma, prob.l, nu, prob.eta, prob.x, prob.sigma, prob.l)
+    K = O.kernel_matrix(prob.x, prob.sigma, prob.l, nu)
+    ref = prob.eta ** 2 * np.linalg.solve(K + prob.eta ** 2 * np.eye(prob.n), K).T
+    assert np.abs(C - ref).max() < 1e-10 * np.abs(ref).max()
+
+
+def test_posterior_cov_is_psd_below_prior_and_prior_far_away():
+    prob = inputs.random_small(1, 80, seed=33, nu=1.5, eta=0.1, constant_scales=True)
+    xt = np.concatenate([np.linspace(0, 1, 7), [40.0]])[:, None]
+    st = np.full(8, prob.sigma[0])
+    lt = np.full(8, prob.l[0])
+    C = O.posterior_cov_exact(prob.x, prob.sigma, prob.l, 1.5, prob.eta, xt, st, lt)
+    assert np.abs(C - C.T).max() < 1e-12
+    assert np.linalg.eigvalsh(0.5 * (C + C.T)).min() > -1e-12
+    assert np.all(np.diag(C) <= st ** 2 + 1e-14)
+    # inside the data the variance is reduced; far away it returns to the prior
+    assert np.all(np.diag(C)[:7] < 0.5 * st[:7] ** 2)
+    assert abs(C[7, 7] - st[7] ** 2) < 1e-12
+
+
+def test_ktilde_posterior_cov_noise_identity_and_psd():
+    """The K~ version (every term from K~ entries) obeys the same identity at the
+    training points and is positive semidefinite over targets."""
+    prob, sp, scale = _small_case(1, 1.5, 24, seed=34, lmin=0.2, lmax=0.3)
+    p = _params(1, 1.5, sp, 6, 0.1, 60, eps=1e-6, center=(0.5, 0, 0), scale=scale)
+    Kt = O.ktilde_entries(p, prob.x, prob.sigma, prob.l)
+    C = O.ktilde_posterior_cov(p, prob.x, prob.sigma, prob.l, 0.2, prob.x, prob.sigma, prob.l)
+    ref = 0.04 * np.linalg.solve(Kt + 0.04 * np.eye(prob.n), Kt).T
+    assert np.abs(C - ref).max() < 1e-10 * np.abs(ref).max()
+    xt = np.linspace(0.05, 0.95, 5)[:, None]
+    st, lt = np.full(5, 1.0), np.full(5, 0.25)
+    Ck = O.ktilde_posterior_cov(p, prob.x, prob.sigma, prob.l, 0.2, xt, st, lt)
+    assert np.abs(Ck - Ck.T).max() < 1e-12
+    assert np.linalg.eigvalsh(Ck).min() > -1e-12
