@@ -272,6 +272,18 @@ int gp_server_stats(gp_server_t srv, gp_server_counters* out);
 /* Finish every queued request, then stop the workers and free the server. */
 int gp_server_destroy(gp_server_t srv);
 
+/* The numbers gp_plan would choose (N_sigma, the t grid, Delta-omega, M, the
+ * window, the FFT length and active box, n_pairs; device_bytes and a_rows are
+ * 0) for d-dimensional points whose bounding box has largest side `extent`
+ * (the box's largest side if opts.use_box) and length scales in
+ * [l_min, l_max], from those ranges alone: host arithmetic only, no device
+ * memory or data.  Section 3 gives the discretisation these rules size
+ * (lemma lem:interp, lemma lem:dt, eq:PSF, the spectral tail of the Matern
+ * density); the readings are those of gp_plan.  Errors: GP_EINVAL, GP_EDOMAIN,
+ * GP_EUNSUPPORTED as gp_plan. */
+int gp_plan_rules(int d, double nu, double tol, double l_min, double l_max, double extent,
+                  const gp_opts* opts, gp_plan_params* out);
+
 /* Change the stream later work of this plan is ordered on. */
 int gp_plan_set_stream(gp_plan_t plan, void* stream);
 

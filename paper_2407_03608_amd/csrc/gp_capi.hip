@@ -190,43 +190,80 @@ int gp_plan_query(int d, int64_t n, const double* pts, const double* sigma, cons
   });
 }
 
+static void fill_params(const Plan& P, gp_plan_params* o) {
+  std::memset(o, 0, sizeof(*o));
+  o->d = P.d;
+  o->n = P.n;
+  o->precision = P.precision;
+  o->nu = P.nu;
+  o->eta = P.eta;
+  o->t_min = P.t_min;
+  o->t_max = P.t_max;
+  o->n_t = P.n_t;
+  o->s_min = P.s_min;
+  o->s_max = P.s_max;
+  o->n_sigma = P.n_sigma;
+  o->dw = P.dw;
+  o->M = P.M;
+  for (int r = 0; r < 3; ++r) {
+    o->center[r] = P.center[r];
+    o->nf[r] = P.nf[r];
+    o->lo[r] = P.lo[r];
+    o->na[r] = P.na[r];
+    o->tile[r] = P.tile[r];
+  }
+  o->scale = P.scale;
+  o->w = P.w;
+  o->beta = P.beta;
+  o->nufft_tol = P.nufft_tol;
+  o->n_pairs = P.npair;
+  o->device_bytes = P.device_bytes;
+  o->pred_tail = P.pred_tail;
+  o->m_capped = P.m_capped;
+  o->step3 = P.step3;
+  o->spread = P.spread_owner ? 0 : 1;
+  o->interp = P.interp_mode;
+  o->a_rows = P.a_rows;
+}
+
 int gp_plan_info(gp_plan_t h, gp_plan_params* o) {
   return guarded([&] {
     if (!h || !o) throw Error{GP_EINVAL, "null argument"};
-    const Plan& P = h->P;
-    std::memset(o, 0, sizeof(*o));
-    o->d = P.d;
-    o->n = P.n;
-    o->precision = P.precision;
-    o->nu = P.nu;
-    o->eta = P.eta;
-    o->t_min = P.t_min;
-    o->t_max = P.t_max;
-    o->n_t = P.n_t;
-    o->s_min = P.s_min;
-    o->s_max = P.s_max;
-    o->n_sigma = P.n_sigma;
-    o->dw = P.dw;
-    o->M = P.M;
-    for (int r = 0; r < 3; ++r) {
-      o->center[r] = P.center[r];
-      o->nf[r] = P.nf[r];
-      o->lo[r] = P.lo[r];
-      o->na[r] = P.na[r];
-      o->tile[r] = P.tile[r];
-    }
-    o->scale = P.scale;
-    o->w = P.w;
-    o->beta = P.beta;
-    o->nufft_tol = P.nufft_tol;
-    o->n_pairs = P.npair;
-    o->device_bytes = P.device_bytes;
-    o->pred_tail = P.pred_tail;
-    o->m_capped = P.m_capped;
-    o->step3 = P.step3;
-    o->spread = P.spread_owner ? 0 : 1;
-    o->interp = P.interp_mode;
-    o->a_rows = P.a_rows;
+    fill_params(h->P, o);
+    return GP_OK;
+  });
+}
+
+int gp_plan_rules(int d, double nu, double tol, double l_min, double l_max, double extent,
+                  const gp_opts* opts_in, gp_plan_params* out) {
+  return guarded([&] {
+    if (!out) throw Error{GP_EINVAL, "null argument"};
+    gp_opts opts;
+    if (opts_in)
+      opts = *opts_in;
+    else
+      gp_opts_init(&opts);
+    if (d < 1 || d > 3) throw Error{GP_EINVAL, "d must be 1, 2 or 3"};
+    if (!(nu > 0)) throw Error{GP_EDOMAIN, "nu must be > 0"};
+    if (!(tol > 0) || !(tol < 1)) throw Error{GP_EDOMAIN, "tol must be in (0, 1)"};
+    if (!(l_min > 0) || !(l_max >= l_min) || !std::isfinite(l_max))
+      throw Error{GP_EDOMAIN, "need 0 < l_min <= l_max < inf"};
+    if (!(extent > 0) || !std::isfinite(extent)) throw Error{GP_EDOMAIN, "extent must be > 0"};
+    if (opts.precision != GP_FP64 && opts.precision != GP_FP32_BULK)
+      throw Error{GP_EINVAL, "unknown precision"};
+    Plan P;
+    P.d = d;
+    P.nu = nu;
+    P.se = std::isinf(nu);
+    P.precision = opts.precision;
+    P.scale = 2.0 / extent;
+    double lmin = l_min, lmax = l_max;
+    if (opts.l_lo > 0) lmin = std::min(lmin, opts.l_lo);
+    if (opts.l_hi > 0) lmax = std::max(lmax, opts.l_hi);
+    choose_params(&P, d, nu, tol, lmin, lmax, opts);
+    P.nk = P.n_sigma + 1;
+    P.npair = (P.nk + 1) / 2;
+    fill_params(P, out);
     return GP_OK;
   });
 }

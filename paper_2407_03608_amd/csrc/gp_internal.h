@@ -185,6 +185,8 @@ struct PhaseScope {
 };
 
 // plan.hip
+void choose_params(Plan* P, int d, double nu, double tol, double lmin, double lmax,
+                   const gp_opts& opts);
 int build_plan(int d, int64_t n, const double* pts, const double* sigma, const double* l,
                double nu, double eta, double tol, const gp_opts* opts, Plan* P, bool query_only,
                size_t* bytes_out);

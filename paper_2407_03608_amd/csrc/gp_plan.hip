@@ -57,6 +57,25 @@ double phi_of_r(double nu, double r) {
   return s * dt;
 }
 
+// Max over the sample radii of |trapezoid sum of eq:trapsum - phi_nu(r)|, the
+// sum over t_j = t_min + j (t_max - t_min)/n_t of u(t_j) exp(-r^2 nu/(2 e^t_j))
+// with halved end weights (eq:maternpres, eq:schoenberg2 at chi^2 = e^t/nu).
+double trap_error(double nu, double tmin, double tmax, int nt, const std::vector<double>& rs,
+                  const std::vector<double>& ref) {
+  const double h = (tmax - tmin) / nt, lg = std::lgamma(nu);
+  double worst = 0;
+  for (size_t i = 0; i < rs.size(); ++i) {
+    double s = 0;
+    for (int j = 0; j <= nt; ++j) {
+      const double t = tmin + j * h;
+      const double f = std::exp(nu * t - std::exp(t) - lg - rs[i] * rs[i] * nu / (2.0 * std::exp(t)));
+      s += (j == 0 || j == nt) ? 0.5 * f : f;
+    }
+    worst = std::max(worst, std::fabs(s * h - ref[i]));
+  }
+  return worst;
+}
+
 // Smallest r with phi_nu(r) <= target (bisection; phi is decreasing).
 double r_at_level(double nu, double target) {
   double lo = 0, hi = 1;
@@ -504,79 +523,12 @@ void build_records_into(Plan* P, int64_t n, const double* pts, const double* sig
 
 // ------------------------------------------------------------ build_plan ----
 
-int build_plan(int d, int64_t n, const double* pts, const double* sigma, const double* l,
-               double nu, double eta, double tol, const gp_opts* opts_in, Plan* P,
-               bool query_only, size_t* bytes_out) {
-  gp_opts opts;
-  if (opts_in)
-    opts = *opts_in;
-  else
-    gp_opts_init(&opts);
-  if (d < 1 || d > 3) throw Error{GP_EINVAL, "d must be 1, 2 or 3"};
-  if (n < 1 || n > (int64_t)std::numeric_limits<int>::max() / 4)
-    throw Error{GP_EINVAL, "n must be in [1, 2^29)"};
-  if (!pts || !sigma || !l) throw Error{GP_EINVAL, "null input pointer"};
-  if (!(nu > 0)) throw Error{GP_EDOMAIN, "nu must be > 0"};
-  if (!(eta >= 0) || !std::isfinite(eta)) throw Error{GP_EDOMAIN, "eta must be finite and >= 0"};
-  if (!(tol > 0) || !(tol < 1)) throw Error{GP_EDOMAIN, "tol must be in (0, 1)"};
-  if (opts.precision != GP_FP64 && opts.precision != GP_FP32_BULK)
-    throw Error{GP_EINVAL, "unknown precision"};
-
-  P->d = d;
-  P->n = n;
-  P->precision = opts.precision;
-  P->nu = nu;
-  P->eta = eta;
-  P->se = std::isinf(nu);
-  P->stream = static_cast<hipStream_t>(opts.stream);
-  hipStream_t s = P->stream;
-
-  // ---- host copies for validation and ranges
-  std::vector<double> hx(n * d), hs(n), hl(n);
-  GP_HIP(hipMemcpyAsync(hx.data(), pts, n * d * sizeof(double), hipMemcpyDeviceToHost, s));
-  GP_HIP(hipMemcpyAsync(hs.data(), sigma, n * sizeof(double), hipMemcpyDeviceToHost, s));
-  GP_HIP(hipMemcpyAsync(hl.data(), l, n * sizeof(double), hipMemcpyDeviceToHost, s));
-  GP_HIP(hipStreamSynchronize(s));
-  double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-  for (int r = 0; r < d; ++r) {
-    lo[r] = std::numeric_limits<double>::infinity();
-    hi[r] = -lo[r];
-  }
-  double lmin = std::numeric_limits<double>::infinity(), lmax = 0;
-  for (int64_t i = 0; i < n; ++i) {
-    for (int r = 0; r < d; ++r) {
-      double v = hx[i * d + r];
-      if (!std::isfinite(v)) throw Error{GP_EDOMAIN, "non-finite point coordinate"};
-      lo[r] = std::min(lo[r], v);
-      hi[r] = std::max(hi[r], v);
-    }
-    if (!(hs[i] > 0) || !std::isfinite(hs[i])) throw Error{GP_EDOMAIN, "sigma must be finite and > 0"};
-    if (!(hl[i] > 0) || !std::isfinite(hl[i])) throw Error{GP_EDOMAIN, "l must be finite and > 0"};
-    lmin = std::min(lmin, hl[i]);
-    lmax = std::max(lmax, hl[i]);
-  }
-  if (opts.use_box) {
-    for (int r = 0; r < d; ++r) {
-      if (!(opts.box_lo[r] <= lo[r] && opts.box_hi[r] >= hi[r]))
-        throw Error{GP_ERANGE, "points outside gp_opts box"};
-      lo[r] = opts.box_lo[r];
-      hi[r] = opts.box_hi[r];
-    }
-  }
-  if (opts.l_lo > 0) lmin = std::min(lmin, opts.l_lo);
-  if (opts.l_hi > 0) lmax = std::max(lmax, opts.l_hi);
-
-  // ---- isotropic map onto [-1,1]^d (section 5 assumes the points lie there)
-  double ext = 0;
-  for (int r = 0; r < d; ++r) {
-    P->center[r] = 0.5 * (lo[r] + hi[r]);
-    ext = std::max(ext, hi[r] - lo[r]);
-  }
-  if (!(ext > 0)) ext = 2.0;
-  P->scale = 2.0 / ext;
-  P->l_range_lo = lmin;
-  P->l_range_hi = lmax;
-
+// The plan's numbers from the problem's ranges alone (no device data): the
+// Chebyshev degree, t grid, Fourier spacing and half-width, window and
+// oversampled grid, the active box and its tiles.  Needs P->d, nu, se,
+// precision and scale (the box map) set; lmin, lmax in the caller's units.
+void choose_params(Plan* P, int d, double nu, double tol, double lmin, double lmax,
+                   const gp_opts& opts) {
   // ---- width range (sigma_p = l'/sqrt 2) and Chebyshev degree (section 3.3)
   const double sq2 = std::sqrt(2.0);
   double smin = lmin * P->scale / sq2, smax = lmax * P->scale / sq2;
@@ -618,11 +570,53 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
     P->t_max = opts.t_max;
     P->n_t = opts.n_t;
   } else {
+    // Closed-form start (the three terms of lemma lem:dt at eps/10 with unit
+    // constants), then the smallest N_t whose trapezoid sum reproduces phi_nu
+    // to eps/10 on sampled r: the lemma leaves its constants open, and the
+    // discretisation term alone is up to 100x larger than e^(-pi^2/dt) for
+    // nu >= 3/2.  N_t costs plan time only (step 3 uses the precomputed tensor).
     const double L10 = std::log(10.0 / eps);
     P->t_min = std::log(eps / 10.0) / nu;
     P->t_max = std::log(2.0 * L10) + 0.5;
     const double dt = PI * PI / L10;
-    P->n_t = (int)std::ceil((P->t_max - P->t_min) / dt);
+    const int n0 = std::max(1, (int)std::ceil((P->t_max - P->t_min) / dt));
+    (void)n0;
+    const double target = eps / 10.0;
+    const double rmax = r_at_level(nu, target);
+    std::vector<double> rs, ref;
+    for (int i = 0; i <= 160; ++i) {
+      rs.push_back(rmax * i / 160.0);
+      ref.push_back(phi_of_r(nu, rs.back()));
+    }
+    auto err = [&](int m) { return trap_error(nu, P->t_min, P->t_max, m, rs, ref); };
+    int nt = n0;
+    for (int round = 0; round < 6; ++round) {
+      int lo = std::max(1, (int)std::ceil((P->t_max - P->t_min) / dt));
+      nt = lo;
+      if (err(lo) <= target) break;
+      // doubling, then bisection for the smallest passing count
+      int hi = lo;
+      bool ok = false;
+      while (hi < 8 * lo) {
+        hi = std::min(2 * hi, 8 * lo);
+        if (err(hi) <= target) {
+          ok = true;
+          break;
+        }
+      }
+      nt = hi;
+      if (!ok) {  // the truncation below t_min dominates: extend the range
+        P->t_min -= std::log(10.0) / nu;
+        continue;
+      }
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) / 2;
+        (err(mid) <= target ? hi : lo) = mid;
+      }
+      nt = hi;
+      break;
+    }
+    P->n_t = nt;
   }
   P->nt_eff = P->se ? 1 : P->n_t + 1;
 
@@ -735,6 +729,84 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
   // tiles further along each dimension
   P->nsrc = 2;
   for (int r = 0; r < d; ++r) P->nsrc = std::max(P->nsrc, (P->w - 2) / P->tile[r] + 2);
+}
+
+int build_plan(int d, int64_t n, const double* pts, const double* sigma, const double* l,
+               double nu, double eta, double tol, const gp_opts* opts_in, Plan* P,
+               bool query_only, size_t* bytes_out) {
+  gp_opts opts;
+  if (opts_in)
+    opts = *opts_in;
+  else
+    gp_opts_init(&opts);
+  if (d < 1 || d > 3) throw Error{GP_EINVAL, "d must be 1, 2 or 3"};
+  if (n < 1 || n > (int64_t)std::numeric_limits<int>::max() / 4)
+    throw Error{GP_EINVAL, "n must be in [1, 2^29)"};
+  if (!pts || !sigma || !l) throw Error{GP_EINVAL, "null input pointer"};
+  if (!(nu > 0)) throw Error{GP_EDOMAIN, "nu must be > 0"};
+  if (!(eta >= 0) || !std::isfinite(eta)) throw Error{GP_EDOMAIN, "eta must be finite and >= 0"};
+  if (!(tol > 0) || !(tol < 1)) throw Error{GP_EDOMAIN, "tol must be in (0, 1)"};
+  if (opts.precision != GP_FP64 && opts.precision != GP_FP32_BULK)
+    throw Error{GP_EINVAL, "unknown precision"};
+
+  P->d = d;
+  P->n = n;
+  P->precision = opts.precision;
+  P->nu = nu;
+  P->eta = eta;
+  P->se = std::isinf(nu);
+  P->stream = static_cast<hipStream_t>(opts.stream);
+  hipStream_t s = P->stream;
+
+  // ---- host copies for validation and ranges
+  std::vector<double> hx(n * d), hs(n), hl(n);
+  GP_HIP(hipMemcpyAsync(hx.data(), pts, n * d * sizeof(double), hipMemcpyDeviceToHost, s));
+  GP_HIP(hipMemcpyAsync(hs.data(), sigma, n * sizeof(double), hipMemcpyDeviceToHost, s));
+  GP_HIP(hipMemcpyAsync(hl.data(), l, n * sizeof(double), hipMemcpyDeviceToHost, s));
+  GP_HIP(hipStreamSynchronize(s));
+  double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  for (int r = 0; r < d; ++r) {
+    lo[r] = std::numeric_limits<double>::infinity();
+    hi[r] = -lo[r];
+  }
+  double lmin = std::numeric_limits<double>::infinity(), lmax = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    for (int r = 0; r < d; ++r) {
+      double v = hx[i * d + r];
+      if (!std::isfinite(v)) throw Error{GP_EDOMAIN, "non-finite point coordinate"};
+      lo[r] = std::min(lo[r], v);
+      hi[r] = std::max(hi[r], v);
+    }
+    if (!(hs[i] > 0) || !std::isfinite(hs[i])) throw Error{GP_EDOMAIN, "sigma must be finite and > 0"};
+    if (!(hl[i] > 0) || !std::isfinite(hl[i])) throw Error{GP_EDOMAIN, "l must be finite and > 0"};
+    lmin = std::min(lmin, hl[i]);
+    lmax = std::max(lmax, hl[i]);
+  }
+  if (opts.use_box) {
+    for (int r = 0; r < d; ++r) {
+      if (!(opts.box_lo[r] <= lo[r] && opts.box_hi[r] >= hi[r]))
+        throw Error{GP_ERANGE, "points outside gp_opts box"};
+      lo[r] = opts.box_lo[r];
+      hi[r] = opts.box_hi[r];
+    }
+  }
+  if (opts.l_lo > 0) lmin = std::min(lmin, opts.l_lo);
+  if (opts.l_hi > 0) lmax = std::max(lmax, opts.l_hi);
+
+  // ---- isotropic map onto [-1,1]^d (section 5 assumes the points lie there)
+  double ext = 0;
+  for (int r = 0; r < d; ++r) {
+    P->center[r] = 0.5 * (lo[r] + hi[r]);
+    ext = std::max(ext, hi[r] - lo[r]);
+  }
+  if (!(ext > 0)) ext = 2.0;
+  P->scale = 2.0 / ext;
+  P->l_range_lo = lmin;
+  P->l_range_hi = lmax;
+
+  choose_params(P, d, nu, tol, lmin, lmax, opts);
+  const int nf = P->nf[0];
+  const double smin = P->s_min, smax = P->s_max;
   P->nk = P->n_sigma + 1;
   P->npair = (P->nk + 1) / 2;
 

@@ -121,6 +121,7 @@ EXPORTS = [
     "gp_last_error",
     "gp_residual",
     "gp_posterior_cov",
+    "gp_plan_rules",
     "gp_plan_set_timing",
     "gp_plan_get_timing",
     "gp_server_opts_init",
@@ -230,6 +231,9 @@ def load(path: str = LIB_PATH):
     L.gp_residual.restype = _c_i
     L.gp_plan_set_timing.argtypes = [_c_p, _c_i]
     L.gp_plan_set_timing.restype = _c_i
+    L.gp_plan_rules.argtypes = [_c_i, _c_d, _c_d, _c_d, _c_d, _c_d, ctypes.POINTER(GpOpts),
+                                ctypes.POINTER(GpPlanParams)]
+    L.gp_plan_rules.restype = _c_i
     L.gp_posterior_cov.argtypes = [_c_p, _c_i64, _c_p, _c_p, _c_p, _c_d, _c_i, _c_p, _c_p,
                                    ctypes.POINTER(GpCgInfo)]
     L.gp_posterior_cov.restype = _c_i
@@ -271,7 +275,7 @@ def _dev(t: torch.Tensor, name: str) -> torch.Tensor:
     return t.contiguous()
 
 
-def make_opts(precision: int = GP_FP64, stream=None, **kw) -> GpOpts:
+def make_opts(precision: int = GP_FP64, stream=None, host_only: bool = False, **kw) -> GpOpts:
     o = GpOpts()
     _check(load().gp_opts_init(ctypes.byref(o)))
     o.precision = precision
@@ -285,8 +289,9 @@ def make_opts(precision: int = GP_FP64, stream=None, **kw) -> GpOpts:
             o.use_box = 1
         else:
             setattr(o, k, v)
-    s = stream if stream is not None else torch.cuda.current_stream()
-    o.stream = ctypes.c_void_p(s.cuda_stream)
+    if not host_only:
+        s = stream if stream is not None else torch.cuda.current_stream()
+        o.stream = ctypes.c_void_p(s.cuda_stream)
     return o
 
 
@@ -410,6 +415,24 @@ class Plan:
 
 def _info_dict(info: GpCgInfo) -> dict:
     return {name: getattr(info, name) for name, _ in GpCgInfo._fields_}
+
+
+def _params_dict(p: "GpPlanParams") -> dict:
+    out = {}
+    for name, _ in GpPlanParams._fields_:
+        v = getattr(p, name)
+        out[name] = list(v) if hasattr(v, "__len__") else v
+    return out
+
+
+def plan_rules(d: int, nu: float, tol: float, l_min: float, l_max: float, extent: float = 1.0,
+               precision: int = GP_FP64, **opts) -> dict:
+    """gp_plan_rules: the plan's numbers from the problem's ranges (host only)."""
+    o = make_opts(precision, host_only=True, **opts)
+    p = GpPlanParams()
+    _check(load().gp_plan_rules(int(d), float(nu), float(tol), float(l_min), float(l_max),
+                                float(extent), ctypes.byref(o), ctypes.byref(p)))
+    return _params_dict(p)
 
 
 def plan_query(x, sigma, l, nu, eta, tol, precision=GP_FP64, **opts) -> int:
