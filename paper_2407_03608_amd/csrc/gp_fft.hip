@@ -12,8 +12,6 @@
 // Pruning both windows keeps the empty border of the oversampled grid (points
 // fill a fraction 2*Delta-omega of the period) and the discarded high
 // frequencies out of HBM.
-#include <cstdlib>
-
 #include "gp_internal.h"
 
 namespace gp {
@@ -348,6 +346,20 @@ void launch_len(const FftPass& q, const void* in, void* out, const void* tw, hip
   p.L4 = q.L4 > 0 ? q.L4 : 1;
   p.tw4_mod = q.L4 > 0 ? (q.L4 / L) : 1;
   p.tw4_at_load = q.tw4_at_load;
+  // 8192-point passes with 16 elements per thread (512 threads, half the
+  // VGPRs of 32 per thread, so twice the waves per CU to cover the memory
+  // latency); fp32 column passes keep 32 per thread with two columns per
+  // workgroup (measured faster there).
+  if constexpr (L == 8192) {
+    if (sizeof(T) == 8 || q.inner == 1) {
+      if (p.ntrans <= 0) return;
+      hipLaunchKernelGGL((fft_pass_kernel<T, L, 16, 1>), dim3((unsigned)p.ntrans), dim3(L / 16),
+                         0, s, static_cast<const V*>(in), static_cast<V*>(out),
+                         static_cast<const V*>(tw), static_cast<const V*>(q.tw4), p);
+      GP_CHECK_LAUNCH();
+      return;
+    }
+  }
   // Long strided (column) transforms: two columns per workgroup, so pairs of
   // adjacent lanes read adjacent elements of one cache line.
   if constexpr (B == 1 && L >= 6144) {
@@ -355,20 +367,6 @@ void launch_len(const FftPass& q, const void* in, void* out, const void* tw, hip
       const int64_t nb2 = (p.ntrans + 1) / 2;
       if (nb2 <= 0) return;
       hipLaunchKernelGGL((fft_pass_kernel<T, L, EPT, 2>), dim3((unsigned)nb2), dim3(2 * (L / EPT)),
-                         0, s, static_cast<const V*>(in), static_cast<V*>(out),
-                         static_cast<const V*>(tw), static_cast<const V*>(q.tw4), p);
-      GP_CHECK_LAUNCH();
-      return;
-    }
-  }
-  if constexpr (L == 8192 && sizeof(T) == 8) {
-    static const int e16 = [] {
-      const char* e = std::getenv("GPNUFFT_EPT16");
-      return e ? std::atoi(e) : 0;
-    }();
-    if (q.inner == 1 && e16) {
-      if (p.ntrans <= 0) return;
-      hipLaunchKernelGGL((fft_pass_kernel<T, L, 16, 1>), dim3((unsigned)p.ntrans), dim3(L / 16),
                          0, s, static_cast<const V*>(in), static_cast<V*>(out),
                          static_cast<const V*>(tw), static_cast<const V*>(q.tw4), p);
       GP_CHECK_LAUNCH();

@@ -55,6 +55,7 @@ struct NuArgs {
   int64_t pair_stride;
   int64_t grid_off;
   int g0, gc, nsrc;
+  int slot_pairs;  // grid pairs per partial tile slot (min(kGC, npair))
   double eta2;
   int add_noise, first_chunk;
 };
@@ -86,6 +87,8 @@ __global__ __launch_bounds__(kThreads) void spread_owner_kernel(
   T* s_rec = reinterpret_cast<T*>(smem);          // [kPB][ls]
   T* s_x = s_rec + kPB * ls;                      // [kPB]
   int* s_cell = reinterpret_cast<int*>(s_x + kPB);  // [kPB][D]
+  int* s_map = s_cell + kPB * D;                    // [kPB] staged point -> sorted index
+  int* s_np = s_map + kPB;                          // staged count
 
   // no work list: one item per tile, all of its sources, written to the grid
   const int4 wk = work ? work[blockIdx.x] : make_int4((int)blockIdx.x, 0, INT_MAX, -1);
@@ -139,16 +142,41 @@ __global__ __launch_bounds__(kThreads) void spread_owner_kernel(
     const int b0 = bin_start[bin], cnt = bin_start[bin + 1] - b0;
     const int p0 = b0 + max(src_lo - pos, 0), p1 = b0 + min(src_hi - pos, cnt);
     pos += cnt;
+    // Along a dimension where this source bin lies before the tile, a point
+    // reaches the tile only if the last cell of its window does: wave 0
+    // filters each batch of candidates and compacts the survivors (ballot),
+    // so only they are staged and tested by every thread.
+    int offmask = 0;
+    {
+      int q2 = sb;
+      for (int r = 0; r < D; ++r) {
+        if (q2 % a.nsrc) offmask |= 1 << r;
+        q2 /= a.nsrc;
+      }
+    }
     for (int pb = p0; pb < p1; pb += kPB) {
-      const int np = min(kPB, p1 - pb);
+      const int nc = min(kPB, p1 - pb);
       __syncthreads();
+      if (threadIdx.x < kPB) {  // wave 0 (kPB is the wavefront size)
+        bool keep = (int)threadIdx.x < nc;
+        if (keep && offmask)
+          for (int r = 0; r < D; ++r)
+            if ((offmask >> r) & 1) keep = keep && cell[r * a.n + pb + threadIdx.x] + w - 1 >= t0[r];
+        const unsigned long long m = __ballot(keep);
+        if (keep) s_map[__popcll(m & ((1ull << threadIdx.x) - 1ull))] = pb + threadIdx.x;
+        if (threadIdx.x == 0) *s_np = __popcll(m);
+      }
+      __syncthreads();
+      const int np = *s_np;
+      if (np == 0) continue;
       for (int e = threadIdx.x; e < np * rs; e += kThreads) {
-        const int p = e / rs;
-        s_rec[p * ls + (e - p * rs)] = pw[(int64_t)pb * rs + e];
+        const int p = e / rs, c = e - p * rs;
+        s_rec[p * ls + c] = pw[(int64_t)s_map[p] * rs + c];
       }
       if (threadIdx.x < np) {
-        s_x[threadIdx.x] = (T)x[pb + threadIdx.x];
-        for (int r = 0; r < D; ++r) s_cell[threadIdx.x * D + r] = cell[r * a.n + pb + threadIdx.x];
+        const int i = s_map[threadIdx.x];
+        s_x[threadIdx.x] = (T)x[i];
+        for (int r = 0; r < D; ++r) s_cell[threadIdx.x * D + r] = cell[r * a.n + i];
       }
       __syncthreads();
       for (int p = 0; p < np; ++p) {
@@ -189,7 +217,7 @@ __global__ __launch_bounds__(kThreads) void spread_owner_kernel(
       const int l = threadIdx.x + c * kThreads;
 #pragma unroll
       for (int g = 0; g < kGC; ++g)
-        if (g < a.gc) part[((int64_t)slot * kGC + g) * tcells + l] = acc[c][g];
+        if (g < a.gc) part[((int64_t)slot * a.slot_pairs + g) * tcells + l] = acc[c][g];
       continue;
     }
     const int64_t gi = a.grid_off + (int64_t)cx[c] * a.gstride[0] + (int64_t)cy[c] * a.gstride[1] +
@@ -222,7 +250,7 @@ __global__ __launch_bounds__(kThreads) void spread_reduce_kernel(
     const int g = e / tcells, l = e - g * tcells;
     V v = V{T(0), T(0)};
     for (int j = 0; j < wk.z; ++j) {
-      const V u = part[((int64_t)(wk.y + j) * kGC + g) * tcells + l];
+      const V u = part[((int64_t)(wk.y + j) * a.slot_pairs + g) * tcells + l];
       v.x += u.x;
       v.y += u.y;
     }
@@ -682,6 +710,7 @@ NuArgs nu_args(const Plan* P, const Records& R) {
     a.grid_off = 0;
   }
   a.nsrc = P->nsrc;
+  a.slot_pairs = std::min(kGC, P->npair);
   a.g0 = 0;
   a.gc = 0;
   a.eta2 = P->eta * P->eta;
@@ -692,7 +721,8 @@ NuArgs nu_args(const Plan* P, const Records& R) {
 
 template <typename T>
 size_t spread_owner_smem(const Plan* P, int rs) {
-  return kPB * (lds_stride(rs) + 1) * sizeof(T) + kPB * P->d * sizeof(int) + 16;
+  static_assert(kPB == 64, "the spread pre-filter compacts one batch per wavefront");
+  return kPB * (lds_stride(rs) + 1) * sizeof(T) + (kPB * P->d + kPB + 1) * sizeof(int) + 16;
 }
 
 template <typename T, int D, int CPT>

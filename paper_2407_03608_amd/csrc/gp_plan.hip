@@ -315,12 +315,20 @@ __global__ void atab_kernel(int64_t rows, int npk, int nkp, int nk, int nt,
 // training points at plan time and for posterior targets).
 struct Records;  // fwd (defined in nufft.hip via Plan buffers)
 
-// Chunk sizes of the work lists: at least a minimum, and large enough that
-// one launch has no more than about kTargetItems chunked items.
-constexpr int64_t kTargetItems = 2048;
+// Chunk sizes of the work lists: a tile (bin) is split when it holds more
+// than kImbalance times the mean load, so the densest tiles of clustered
+// points do not serialise a launch; at least kMin*Chunk per item, and never
+// more than about kMaxItems chunked items.
+constexpr int64_t kImbalance = 4;
+constexpr int64_t kMaxItems = 65536;
 constexpr int64_t kMinSpreadChunk = 256;
 constexpr int64_t kMinInterpChunk = 64;
-constexpr int kSlotPairs = 8;  // pairs per partial slot (the spread pair-chunk size)
+constexpr int64_t kMinSuperChunk = 128;
+
+static int64_t chunk_size(int64_t total, int64_t units, int64_t min_chunk) {
+  const int64_t mean = (total + std::max<int64_t>(units, 1) - 1) / std::max<int64_t>(units, 1);
+  return std::max({min_chunk, kImbalance * mean, total / kMaxItems});
+}
 
 static int64_t source_total_bound(const Plan* P, int64_t n) {
   int64_t m = 1;
@@ -328,18 +336,21 @@ static int64_t source_total_bound(const Plan* P, int64_t n) {
   return n * m;
 }
 
+static int slot_pairs(const Plan* P) { return (int)std::min<int64_t>(8, P->npair); }
+
 // Device bytes of the work lists and partial tiles, bounded before the bin
 // sort is known (plan query) by the chunk-size rule.
 size_t work_list_bound_bytes(const Plan* P, int64_t n, size_t cs) {
   const int64_t ts = source_total_bound(P, n);
-  const int64_t qs = std::max(kMinSpreadChunk, ts / kTargetItems);
-  const int64_t slots = std::min<int64_t>(2 * kTargetItems + 2, 2 * ts / qs + 2);
+  const int64_t qs = chunk_size(ts, P->n_bins, kMinSpreadChunk);
+  const int64_t slots = 2 * ts / qs + 2;
   const int64_t tcells = (int64_t)P->tile[0] * P->tile[1] * P->tile[2];
   const int64_t items = P->n_bins + ts / qs + 1;
-  const int64_t qi = std::max(kMinInterpChunk, n / kTargetItems);
+  const int64_t qi = chunk_size(n, P->n_bins, kMinInterpChunk);
   const int64_t iitems = P->n_bins + n / qi + 1;
-  const int64_t sitems = P->d == 2 ? P->n_bins / 4 + 2 * P->nbins[0] + n / 128 + 1 : 0;
-  return (size_t)(2 * items + iitems + sitems) * 16 + (size_t)slots * tcells * kSlotPairs * cs;
+  const int64_t nsup = P->n_bins / 4 + 2 * P->nbins[0] + 2;
+  const int64_t sitems = P->d == 2 ? nsup + n / chunk_size(n, nsup, kMinSuperChunk) + 1 : 0;
+  return (size_t)(2 * items + iitems + sitems) * 16 + (size_t)slots * tcells * slot_pairs(P) * cs;
 }
 
 // Build the spread and interpolation work lists from the bin offsets.  The
@@ -376,7 +387,7 @@ static void build_work_lists(Plan* P, Records& R, const std::vector<int>& start,
     src[t] = cnt;
     ts += cnt;
   }
-  const int64_t qs = std::max(kMinSpreadChunk, ts / kTargetItems);
+  const int64_t qs = chunk_size(ts, P->n_bins, kMinSpreadChunk);
   std::vector<int> spw, spr;
   int64_t slots = 0;
   for (int64_t t = 0; t < P->n_bins; ++t) {
@@ -392,7 +403,7 @@ static void build_work_lists(Plan* P, Records& R, const std::vector<int>& start,
     spr.insert(spr.end(), {(int)t, (int)slots, (int)c, 0});
     slots += c;
   }
-  const int64_t qi = std::max(kMinInterpChunk, R.n / kTargetItems);
+  const int64_t qi = chunk_size(R.n, P->n_bins, kMinInterpChunk);
   std::vector<int> inw;
   for (int64_t b = 0; b < P->n_bins; ++b) {
     const int64_t cnt = start[b + 1] - start[b];
@@ -403,11 +414,10 @@ static void build_work_lists(Plan* P, Records& R, const std::vector<int>& start,
   }
   // 2x2 super-bins (d = 2): the points of bin rows 2sy and 2sy+1, bins
   // 2sx..2sx+1 of each, in that order
-  const int64_t kSuperChunkMin = 128;
   std::vector<int> inw2;
   if (d == 2) {
-    const int64_t q2 = std::max(kSuperChunkMin, R.n / kTargetItems);
     const int nsb0 = (P->nbins[0] + 1) / 2, nsb1 = (P->nbins[1] + 1) / 2;
+    const int64_t q2 = chunk_size(R.n, (int64_t)nsb0 * nsb1, kMinSuperChunk);
     for (int sy = 0; sy < nsb1; ++sy)
       for (int sx = 0; sx < nsb0; ++sx) {
         const int bx0 = 2 * sx, bx1 = std::min(2 * sx + 1, P->nbins[0] - 1);
@@ -439,7 +449,7 @@ static void build_work_lists(Plan* P, Records& R, const std::vector<int>& start,
     R.sp_red.alloc(spr.size() * sizeof(int));
     GP_HIP(hipMemcpyAsync(R.sp_red.p, spr.data(), spr.size() * sizeof(int), hipMemcpyHostToDevice, s));
     const int64_t tcells = (int64_t)P->tile[0] * P->tile[1] * P->tile[2];
-    R.part.alloc((size_t)slots * tcells * kSlotPairs * cs);
+    R.part.alloc((size_t)slots * tcells * slot_pairs(P) * cs);
   }
   if (!inw.empty()) {
     R.in_work.alloc(inw.size() * sizeof(int));
