@@ -29,6 +29,8 @@
  *  - A plan copies what it needs at creation and keeps no reference to the
  *    caller's buffers.  One thread may use a plan at a time; distinct plans
  *    are independent and may be used concurrently on distinct streams.
+ *  - Results are deterministic: every reduction has a fixed order, so the
+ *    same inputs and options give the same bits, alone or next to other work.
  */
 #ifndef GPNUFFT_H
 #define GPNUFFT_H
@@ -156,7 +158,11 @@ int gp_matvec(gp_plan_t plan, const double* alpha, double* out, int add_noise);
  * Stops when the recursive residual ||r||/||y|| <= tol or after max_iter
  * iterations (GP_ENOCONV, alpha = last iterate).  Vector arithmetic and dot
  * products are fp64 in both precisions; the residual is recomputed from the
- * operator every `replace_every` iterations (0 = never). */
+ * operator every `replace_every` iterations (0 = never).  The stopping test
+ * runs on the device and the host queues iterations in batches, reading the
+ * result between them: alpha and info->iters are those of a loop that tests
+ * after every iteration (a few queued iterations past convergence do no
+ * update). */
 int gp_cg_solve(gp_plan_t plan, const double* y, double* alpha, int use_x0, double tol,
                 int max_iter, int replace_every, gp_cg_info* info);
 
