@@ -263,6 +263,126 @@ __global__ __launch_bounds__(kThreads) void spread_reduce_kernel(
   }
 }
 
+// ----------------------------------------------------- spread (sub-tiles) ----
+// Owner-computes on sub-tiles of st^D cells (st = 8 in 2-D, 4 in 3-D) with one
+// wavefront per sub-tile and one cell per lane.  A point then costs one
+// wavefront-check per sub-tile it reaches instead of every thread of a whole
+// tile: about 2.3x (2-D) and 3.4x (3-D) fewer vector instructions, for more
+// staging of the point rows.  Candidates (the points of the bins whose windows
+// can reach the sub-tile) are filtered by the window's extent along every
+// dimension and compacted by ballot; the summation order is the sorted order,
+// as in spread_owner_kernel.
+constexpr int kSubThreads = 64;
+template <typename T, int D>
+__global__ __launch_bounds__(kSubThreads) void spread_sub_kernel(
+    NuArgs a, int st, const double* __restrict__ x, const int* __restrict__ cell,
+    const T* __restrict__ pw, int rs, const int* __restrict__ bin_start,
+    typename V2<T>::type* __restrict__ grid) {
+  using V = typename V2<T>::type;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int ls = lds_stride(rs);
+  T* s_rec = reinterpret_cast<T*>(smem);            // [kPB][ls]
+  T* s_x = s_rec + kPB * ls;                        // [kPB]
+  int* s_cell = reinterpret_cast<int*>(s_x + kPB);  // [kPB][D]
+  int* s_map = s_cell + kPB * D;                    // [kPB]
+  int* s_np = s_map + kPB;
+
+  const int per = a.tile[0] / st;  // sub-tiles per tile side (tiles are cubes)
+  int nsub = 1;
+  for (int r = 0; r < D; ++r) nsub *= per;
+  const int64_t bin = blockIdx.x / nsub;
+  int sub = (int)(blockIdx.x % nsub);
+  int tcoord[3] = {0, 0, 0}, s0[3] = {0, 0, 0};
+  {
+    int64_t tb = bin;
+    for (int r = 0; r < D; ++r) {
+      tcoord[r] = (int)(tb % a.nbins[r]);
+      tb /= a.nbins[r];
+      s0[r] = tcoord[r] * a.tile[r] + (sub % per) * st;
+      sub /= per;
+    }
+  }
+  int l = threadIdx.x;
+  bool mine = true;
+  int c[3] = {0, 0, 0};
+  for (int r = 0; r < D; ++r) {
+    c[r] = s0[r] + l % st;
+    l /= st;
+  }
+  if (l != 0) mine = false;  // lanes beyond st^D own no cell
+
+  V acc[kGC];
+#pragma unroll
+  for (int g = 0; g < kGC; ++g) acc[g] = V{T(0), T(0)};
+  const int w = a.w;
+  const int wko = D * w + 2 * a.g0;
+  int nsrc_tot = 1;
+  for (int r = 0; r < D; ++r) nsrc_tot *= a.nsrc;
+  for (int sb = 0; sb < nsrc_tot; ++sb) {
+    int64_t b = 0, mul = 1;
+    bool ok = true;
+    int q = sb;
+    for (int r = 0; r < D; ++r) {
+      const int br = tcoord[r] - (q % a.nsrc);
+      q /= a.nsrc;
+      if (br < 0) ok = false;
+      b += (int64_t)br * mul;
+      mul *= a.nbins[r];
+    }
+    if (!ok) continue;
+    const int p0 = bin_start[b], p1 = bin_start[b + 1];
+    for (int pb = p0; pb < p1; pb += kPB) {
+      const int nc = min(kPB, p1 - pb);
+      __syncthreads();
+      bool keep = (int)threadIdx.x < nc;
+      if (keep)
+        for (int r = 0; r < D; ++r) {
+          const int cr = cell[r * a.n + pb + threadIdx.x];
+          keep = keep && cr + w - 1 >= s0[r] && cr < s0[r] + st;
+        }
+      const unsigned long long m = __ballot(keep);
+      if (keep) s_map[__popcll(m & ((1ull << threadIdx.x) - 1ull))] = pb + threadIdx.x;
+      const int np = __popcll(m);
+      __syncthreads();
+      if (np == 0) continue;
+      for (int e = threadIdx.x; e < np * rs; e += kSubThreads) {
+        const int p = e / rs, cc = e - p * rs;
+        s_rec[p * ls + cc] = pw[(int64_t)s_map[p] * rs + cc];
+      }
+      if ((int)threadIdx.x < np) {
+        const int i = s_map[threadIdx.x];
+        s_x[threadIdx.x] = (T)x[i];
+        for (int r = 0; r < D; ++r) s_cell[threadIdx.x * D + r] = cell[r * a.n + i];
+      }
+      __syncthreads();
+      for (int p = 0; p < np; ++p) {
+        const T* pr = s_rec + p * ls;
+        const unsigned d0 = (unsigned)(c[0] - s_cell[p * D]);
+        const unsigned d1 = (unsigned)(c[1] - s_cell[p * D + 1]);
+        const unsigned d2 = D > 2 ? (unsigned)(c[2] - s_cell[p * D + 2]) : 0u;
+        bool hit = d0 < (unsigned)w && d1 < (unsigned)w;
+        if (D > 2) hit = hit && d2 < (unsigned)w;
+        if (hit) {
+          T v = pr[d0] * s_x[p] * pr[w + d1];
+          if (D > 2) v *= pr[2 * w + d2];
+#pragma unroll
+          for (int g = 0; g < kGC; ++g)
+            if (g < a.gc) {
+              acc[g].x += v * pr[wko + 2 * g];
+              acc[g].y += v * pr[wko + 2 * g + 1];
+            }
+        }
+      }
+    }
+  }
+  if (!mine) return;
+  const int64_t gi = a.grid_off + (int64_t)c[0] * a.gstride[0] + (int64_t)c[1] * a.gstride[1] +
+                     (int64_t)c[2] * a.gstride[2];
+#pragma unroll
+  for (int g = 0; g < kGC; ++g)
+    if (g < a.gc) grid[(int64_t)(a.g0 + g) * a.pair_stride + gi] = acc[g];
+}
+
 // ---------------------------------------------------------------- spread ----
 // One workgroup per tile of the active grid and chunk of complex grids.  The
 // sources are the bins whose points' windows can reach the tile (nsrc per
@@ -803,9 +923,37 @@ void launch_interp(Plan* P, const Records& R, const double* xs, double* ys, int 
   }
 }
 
+template <typename T, int D>
+void launch_spread_sub(Plan* P, const Records& R, const double* xs, int st) {
+  PhaseScope ps(P, PH_SPREAD);
+  NuArgs a = nu_args(P, R);
+  const int gc = std::min(kGC, P->npair);
+  const int nch = (P->npair + gc - 1) / gc;
+  int nsub = 1;
+  for (int r = 0; r < D; ++r) nsub *= P->tile[0] / st;
+  const size_t smem = spread_owner_smem<T>(P, R.rs);
+  for (int ch = 0; ch < nch; ++ch) {
+    a.g0 = ch * gc;
+    a.gc = std::min(gc, P->npair - a.g0);
+    hipLaunchKernelGGL((spread_sub_kernel<T, D>), dim3((unsigned)(P->n_bins * nsub)),
+                       dim3(kSubThreads), smem, P->stream, a, st, xs, R.cell.as<int>(),
+                       R.pw.as<T>(), R.rs, R.bin_start.as<int>(),
+                       P->gridA.as<typename V2<T>::type>());
+    GP_CHECK_LAUNCH();
+  }
+}
+
 template <typename T>
 void spread_dispatch(Plan* P, const Records& R, const double* xs) {
   const int tcells = P->tile[0] * P->tile[1] * P->tile[2];
+  // fp32 grids in d >= 2: one wavefront per sub-tile (measured 4-7 % faster
+  // there; 2x slower for fp64, whose 16-byte rows make the staging dominate)
+  if (P->spread_owner && P->d >= 2 && P->precision == GP_FP32_BULK) {
+    const int st = std::min(P->d == 2 ? 8 : 4, P->tile[0]);
+    if (P->d == 2) launch_spread_sub<T, 2>(P, R, xs, st);
+    else launch_spread_sub<T, 3>(P, R, xs, st);
+    return;
+  }
   if (P->spread_owner && tcells <= 2 * kThreads) {
     const bool two = tcells > kThreads;
     if (P->d == 1) two ? launch_spread_owner<T, 1, 2>(P, R, xs) : launch_spread_owner<T, 1, 1>(P, R, xs);
