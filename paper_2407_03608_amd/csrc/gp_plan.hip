@@ -8,6 +8,9 @@
 // matvec works on bin-ordered records (the CG vectors stay in that order).
 #include <algorithm>
 #include <cmath>
+#include <tuple>
+#include <mutex>
+#include <map>
 #include <cstring>
 #include <limits>
 
@@ -77,38 +80,172 @@ double trap_error(double nu, double tmin, double tmax, int nt, const std::vector
 }
 
 // Smallest r with phi_nu(r) <= target (bisection; phi is decreasing).
+// Depends on (nu, target) alone, so results are cached.
 double r_at_level(double nu, double target) {
+  static std::mutex mu;
+  static std::map<std::pair<double, double>, double> cache;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find({nu, target});
+    if (it != cache.end()) return it->second;
+  }
   double lo = 0, hi = 1;
   while (phi_of_r(nu, hi) > target && hi < 1e4) hi *= 2;
   for (int it = 0; it < 80; ++it) {
     double mid = 0.5 * (lo + hi);
     (phi_of_r(nu, mid) > target ? lo : hi) = mid;
   }
+  std::lock_guard<std::mutex> lk(mu);
+  cache[{nu, target}] = hi;
   return hi;
 }
 
-// Fraction of the spectral mass of the stationary kernel with length ell that
-// lies outside the radius Omega (Fourier convention of Appendix D):
-// Matern density (1 + (2 pi ell w)^2/(2 nu))^-(nu + d/2), SE exp(-2 pi^2 ell^2 w^2),
-// integrated radially (w^(d-1) dw) on a logarithmic grid.
-double spectral_tail(double nu, int d, double ell, double Omega) {
-  auto dens = [&](double w) {
-    double a = 2 * PI * ell * w;
-    if (std::isinf(nu)) return std::exp(-0.5 * a * a);
-    return std::pow(1.0 + a * a / (2.0 * nu), -(nu + 0.5 * d));
-  };
-  const double s0 = std::log(1e-8 / ell), s1 = std::log(1e16 / ell);
-  const int ns = 40000;
-  const double ds = (s1 - s0) / ns, sO = std::log(Omega);
-  double tot = 0, tail = 0;
-  for (int i = 0; i <= ns; ++i) {
-    double s = s0 + i * ds, w = std::exp(s);
-    double f = dens(w) * std::pow(w, d);  // w^(d-1) dw = w^d ds
-    double c = (i == 0 || i == ns) ? 0.5 : 1.0;
-    tot += c * f;
-    if (s >= sO) tail += c * f;
+// Continued fraction of the regularized incomplete beta function I_x(a, b)
+// (DLMF 8.17.22), evaluated by the modified Lentz method; for x below the
+// mean (a+1)/(a+b+2) it converges in a few dozen terms.
+double betainc_cf(double a, double b, double x) {
+  const double tiny = 1e-300;
+  double c = 1.0, d = 1.0 - (a + b) * x / (a + 1.0);
+  if (std::fabs(d) < tiny) d = tiny;
+  d = 1.0 / d;
+  double f = d;
+  for (int m = 1; m <= 400; ++m) {
+    const double m2 = 2.0 * m;
+    double num = m * (b - m) * x / ((a + m2 - 1.0) * (a + m2));  // even step
+    d = 1.0 + num * d;
+    c = 1.0 + num / c;
+    if (std::fabs(d) < tiny) d = tiny;
+    if (std::fabs(c) < tiny) c = tiny;
+    d = 1.0 / d;
+    f *= d * c;
+    num = -(a + m) * (a + b + m) * x / ((a + m2) * (a + m2 + 1.0));  // odd step
+    d = 1.0 + num * d;
+    c = 1.0 + num / c;
+    if (std::fabs(d) < tiny) d = tiny;
+    if (std::fabs(c) < tiny) c = tiny;
+    d = 1.0 / d;
+    const double del = d * c;
+    f *= del;
+    if (std::fabs(del - 1.0) < 1e-15) break;
   }
-  return tail / tot;
+  return f;
+}
+
+double betainc_reg(double a, double b, double x) {
+  if (x <= 0.0) return 0.0;
+  if (x >= 1.0) return 1.0;
+  const double lbeta = std::lgamma(a) + std::lgamma(b) - std::lgamma(a + b);
+  if (x < (a + 1.0) / (a + b + 2.0))
+    return std::exp(a * std::log(x) + b * std::log1p(-x) - lbeta) * betainc_cf(a, b, x) / a;
+  return 1.0 - std::exp(b * std::log1p(-x) + a * std::log(x) - lbeta) * betainc_cf(b, a, 1.0 - x) / b;
+}
+
+// Regularized upper incomplete gamma Q(a, x): power series of P below a + 1,
+// Legendre's continued fraction (modified Lentz) above.
+double gammaincc_reg(double a, double x) {
+  if (x <= 0.0) return 1.0;
+  const double lg = std::lgamma(a);
+  if (x < a + 1.0) {
+    double term = 1.0 / a, sum = term;
+    for (int n = 1; n < 1000; ++n) {
+      term *= x / (a + n);
+      sum += term;
+      if (term < sum * 1e-17) break;
+    }
+    return 1.0 - sum * std::exp(-x + a * std::log(x) - lg);
+  }
+  const double tiny = 1e-300;
+  double bq = x + 1.0 - a, c = 1.0 / tiny, d = 1.0 / bq, h = d;
+  for (int i = 1; i < 1000; ++i) {
+    const double an = -i * (i - a);
+    bq += 2.0;
+    d = an * d + bq;
+    if (std::fabs(d) < tiny) d = tiny;
+    c = bq + an / c;
+    if (std::fabs(c) < tiny) c = tiny;
+    d = 1.0 / d;
+    const double del = d * c;
+    h *= del;
+    if (std::fabs(del - 1.0) < 1e-15) break;
+  }
+  return std::exp(-x + a * std::log(x) - lg) * h;
+}
+
+// Fraction of the spectral mass of the stationary kernel with length ell that
+// lies outside the radius Omega (Fourier convention of Appendix D).  In
+// t = 2 pi ell w the Matern density (1 + t^2/(2 nu))^-(nu + d/2) is a
+// multivariate t with 2 nu degrees of freedom, whose mass beyond |t| = T is
+// I_{2nu/(2nu+T^2)}(nu, d/2); the squared exponential's is Gaussian, with
+// mass Q(d/2, T^2/2) beyond T.
+double spectral_tail(double nu, int d, double ell, double Omega) {
+  const double T = 2 * PI * ell * Omega;
+  if (std::isinf(nu)) return gammaincc_reg(0.5 * d, 0.5 * T * T);
+  return betainc_reg(nu, 0.5 * d, 2.0 * nu / (2.0 * nu + T * T));
+}
+
+// t grid of eq:trapsum for (nu, eps): closed-form start (the three terms of
+// lemma lem:dt at eps/10 with unit constants), then the smallest N_t whose
+// trapezoid sum reproduces phi_nu to eps/10 on sampled r.  The lemma leaves
+// its constants open, and the discretisation term alone is up to 100x larger
+// than e^(-pi^2/dt) for nu >= 3/2.  N_t costs plan time only (step 3 uses the
+// precomputed tensor).  Depends on (nu, eps) alone, so results are cached.
+void t_grid_rule(double nu, double eps, double* tmin_out, double* tmax_out, int* nt_out) {
+  static std::mutex mu;
+  static std::map<std::pair<double, double>, std::tuple<double, double, int>> cache;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find({nu, eps});
+    if (it != cache.end()) {
+      std::tie(*tmin_out, *tmax_out, *nt_out) = it->second;
+      return;
+    }
+  }
+  double tmin, tmax;
+  const double L10 = std::log(10.0 / eps);
+  tmin = std::log(eps / 10.0) / nu;
+  tmax = std::log(2.0 * L10) + 0.5;
+  const double dt = PI * PI / L10;
+  const int n0 = std::max(1, (int)std::ceil((tmax - tmin) / dt));
+  const double target = eps / 10.0;
+  const double rmax = r_at_level(nu, target);
+  std::vector<double> rs, ref;
+  for (int i = 0; i <= 160; ++i) {
+    rs.push_back(rmax * i / 160.0);
+    ref.push_back(phi_of_r(nu, rs.back()));
+  }
+  auto err = [&](int m) { return trap_error(nu, tmin, tmax, m, rs, ref); };
+  int nt = n0;
+  for (int round = 0; round < 6; ++round) {
+    int lo = std::max(1, (int)std::ceil((tmax - tmin) / dt));
+    nt = lo;
+    if (err(lo) <= target) break;
+    // doubling, then bisection for the smallest passing count
+    int hi = lo;
+    bool ok = false;
+    while (hi < 8 * lo) {
+      hi = std::min(2 * hi, 8 * lo);
+      if (err(hi) <= target) {
+        ok = true;
+        break;
+      }
+    }
+    nt = hi;
+    if (!ok) {  // the truncation below t_min dominates: extend the range
+      tmin -= std::log(10.0) / nu;
+      continue;
+    }
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) / 2;
+      (err(mid) <= target ? hi : lo) = mid;
+    }
+    nt = hi;
+    break;
+  }
+  std::lock_guard<std::mutex> lk(mu);
+  cache[{nu, eps}] = std::make_tuple(tmin, tmax, nt);
+  *tmin_out = tmin;
+  *tmax_out = tmax;
+  *nt_out = nt;
 }
 
 // Sup over (x, sigma) of the Chebyshev interpolation error of lemma lem:interp,
@@ -119,19 +256,24 @@ double cheb_interp_error(double smin, double smax, int ns) {
     sk[k] = 0.5 * (std::cos(PI * k / ns) + 1.0) * (smax - smin) + smin;
     lam[k] = ((k % 2) ? -1.0 : 1.0) * ((k == 0 || k == ns) ? 0.5 : 1.0);
   }
-  double worst = 0;
   const int nsg = 97, nx = 97;
+  std::vector<double> xs(nx), E((size_t)nx * (ns + 1));  // node Gaussians at the sample x
+  for (int b = 0; b < nx; ++b) {
+    xs[b] = 6.0 * smax * b / (nx - 1);
+    for (int k = 0; k <= ns; ++k) E[(size_t)b * (ns + 1) + k] = std::exp(-xs[b] * xs[b] / (2 * sk[k] * sk[k]));
+  }
+  double worst = 0;
+  std::vector<double> P(ns + 1);
   for (int a = 0; a < nsg; ++a) {
     double s = smin + (smax - smin) * (a + 0.5) / nsg;
     double den = 0;
-    std::vector<double> P(ns + 1);
     for (int k = 0; k <= ns; ++k) den += lam[k] / (s - sk[k]);
     for (int k = 0; k <= ns; ++k) P[k] = lam[k] / (s - sk[k]) / den;
     for (int b = 0; b < nx; ++b) {
-      double x = 6.0 * smax * b / (nx - 1);
       double ap = 0;
-      for (int k = 0; k <= ns; ++k) ap += P[k] * std::exp(-x * x / (2 * sk[k] * sk[k]));
-      worst = std::max(worst, std::fabs(ap - std::exp(-x * x / (2 * s * s))));
+      const double* e = &E[(size_t)b * (ns + 1)];
+      for (int k = 0; k <= ns; ++k) ap += P[k] * e[k];
+      worst = std::max(worst, std::fabs(ap - std::exp(-xs[b] * xs[b] / (2 * s * s))));
     }
   }
   return worst;
@@ -560,8 +702,12 @@ void choose_params(Plan* P, int d, double nu, double tol, double lmin, double lm
     const double target = eps / 10;
     int nb = 1;
     while (2 * (kappa - 1) * std::pow((kappa - 1) / (kappa + 1), nb) > target && nb < 200) ++nb;
-    int ns = 1;
-    while (ns < nb && cheb_interp_error(smin, smax, ns) > target) ++ns;
+    // smallest ns in [1, nb] meeting the target (the error falls with ns)
+    int lo_ns = 0, ns = nb;
+    while (ns - lo_ns > 1) {
+      const int mid = (lo_ns + ns) / 2;
+      (cheb_interp_error(smin, smax, mid) > target ? lo_ns : ns) = mid;
+    }
     if (ns % 2 == 0) ++ns;  // N_sigma + 1 even: grids pack in complex pairs
     P->n_sigma = ns;
   }
@@ -580,53 +726,7 @@ void choose_params(Plan* P, int d, double nu, double tol, double lmin, double lm
     P->t_max = opts.t_max;
     P->n_t = opts.n_t;
   } else {
-    // Closed-form start (the three terms of lemma lem:dt at eps/10 with unit
-    // constants), then the smallest N_t whose trapezoid sum reproduces phi_nu
-    // to eps/10 on sampled r: the lemma leaves its constants open, and the
-    // discretisation term alone is up to 100x larger than e^(-pi^2/dt) for
-    // nu >= 3/2.  N_t costs plan time only (step 3 uses the precomputed tensor).
-    const double L10 = std::log(10.0 / eps);
-    P->t_min = std::log(eps / 10.0) / nu;
-    P->t_max = std::log(2.0 * L10) + 0.5;
-    const double dt = PI * PI / L10;
-    const int n0 = std::max(1, (int)std::ceil((P->t_max - P->t_min) / dt));
-    (void)n0;
-    const double target = eps / 10.0;
-    const double rmax = r_at_level(nu, target);
-    std::vector<double> rs, ref;
-    for (int i = 0; i <= 160; ++i) {
-      rs.push_back(rmax * i / 160.0);
-      ref.push_back(phi_of_r(nu, rs.back()));
-    }
-    auto err = [&](int m) { return trap_error(nu, P->t_min, P->t_max, m, rs, ref); };
-    int nt = n0;
-    for (int round = 0; round < 6; ++round) {
-      int lo = std::max(1, (int)std::ceil((P->t_max - P->t_min) / dt));
-      nt = lo;
-      if (err(lo) <= target) break;
-      // doubling, then bisection for the smallest passing count
-      int hi = lo;
-      bool ok = false;
-      while (hi < 8 * lo) {
-        hi = std::min(2 * hi, 8 * lo);
-        if (err(hi) <= target) {
-          ok = true;
-          break;
-        }
-      }
-      nt = hi;
-      if (!ok) {  // the truncation below t_min dominates: extend the range
-        P->t_min -= std::log(10.0) / nu;
-        continue;
-      }
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) / 2;
-        (err(mid) <= target ? hi : lo) = mid;
-      }
-      nt = hi;
-      break;
-    }
-    P->n_t = nt;
+    t_grid_rule(nu, eps, &P->t_min, &P->t_max, &P->n_t);
   }
   P->nt_eff = P->se ? 1 : P->n_t + 1;
 

@@ -114,8 +114,7 @@ def test_m_is_the_smallest_half_width_meeting_the_spectral_tail(case):
     lpmin = lmin * 2.0 / ext
     M, dw = p["M"], p["dw"]
     tail = _tail(nu, d, lpmin, M * dw)
-    # the library integrates the radial density numerically (agrees to ~0.2%)
-    assert p["pred_tail"] == pytest.approx(tail, rel=1e-2, abs=1e-15)
+    assert p["pred_tail"] == pytest.approx(tail, rel=1e-9, abs=1e-300)
     if p["m_capped"]:
         assert M == (2047 if d > 1 else 1 << 18) and tail > tol
     else:
