@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--solve", action="store_true", help="also time full CG solves to 1e-6")
     ap.add_argument("--max-iter", type=int, default=20000)
     ap.add_argument("--inner-tol", type=float, default=3e-3)
+    ap.add_argument("--replace-every", type=int, default=0,
+                    help="residual recomputation period inside the fp32-bulk inner CG")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="end with one device copy of this size (HBM counter calibration)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -213,6 +215,19 @@ def secondary_workloads(gp, torch, args):
         "plan": {k: info[k] for k in ("n_sigma", "n_t", "dw", "M", "nf", "w", "na", "n_pairs", "device_bytes")}}
     P.close()
     return out
+
+
+def step_model(info, ms):
+    """Whole-matvec bytes under the model that counts full oversampled grids:
+    (N_sigma+1)(4 n_f^d + 4 (2M+1)^d) s + N (2d+7) s, with s the element size
+    (pruning the grids to the active box is a gain against it, not credited)."""
+    d = info["d"]
+    s = 8 if info["precision"] == 0 else 4
+    grids = info["n_sigma"] + 1
+    b = grids * (4 * math.prod(info["nf"][:d]) + 4 * (2 * info["M"] + 1) ** d) * s + info["n"] * (2 * d + 7) * s
+    gbs = b / (ms * 1e-3) / 1e9
+    return {"model": "(N_sigma+1)(4 n_f^d + 4 (2M+1)^d) s + N (2d+7) s", "bytes": b,
+            "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 def cpu_baseline(prob, seconds):
@@ -411,10 +426,12 @@ def main():
                                "sigma=exp(0.3 x1), l=0.02+0.02 x2, eta=0.05, fp64, tol 1e-8",
                    "n": prob.n, "plan": {k: info64[k] for k in ("n_sigma", "n_t", "dw", "M", "nf", "w")}},
         "roofline": rf64,
+        "matvec_model_roofline": step_model(info64, ms64),
         "kernels_ms": kernels64,
         "plan_seconds": round(plan64_s, 3),
         "fp32_bulk": {"value": round(prob.n * args.steps / t32, 1), "unit": "points/s",
-                      "ms_per_step": round(ms32, 4), "roofline": rf32, "kernels_ms": kernels32,
+                      "ms_per_step": round(ms32, 4), "roofline": rf32,
+                      "matvec_model_roofline": step_model(info32, ms32), "kernels_ms": kernels32,
                       "plan": {k: info32[k] for k in ("n_sigma", "n_t", "dw", "M", "nf", "w")},
                       "plan_seconds": round(plan32_s, 3),
                       "rel_diff_vs_fp64_matvec": diff},
@@ -432,13 +449,15 @@ def main():
         # inner fp32-operator CG to 3e-3 (above the fp32 operator's own accuracy,
         # ~2e-4), fp64 residual between passes
         al32, ci32 = gp.cg_solve_refined(P32, P64, Y, tol=1e-6, inner_tol=args.inner_tol,
-                                         max_iter=args.max_iter, max_refine=10)
+                                         max_iter=args.max_iter, max_refine=10,
+                                         replace_every=args.replace_every)
         torch.cuda.synchronize()
         s32 = time.perf_counter() - t0
         out["cg_solve"] = {
             "fp64": {"seconds": round(s64, 3), "iters": ci64["iters"], "status": ci64["status"],
                      "rel_res_true": r64},
             "fp32_bulk_refined": {"seconds": round(s32, 3), "iters": ci32["iters"],
+                                  "inner_tol": args.inner_tol, "replace_every": args.replace_every,
                                   "refinements": ci32["refinements"], "status": ci32["status"],
                                   "rel_res_true_fp64_operator": ci32["rel_res_true"],
                                   "rel_diff_vs_fp64_solution":
