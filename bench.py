@@ -70,7 +70,8 @@ def log(*a):
 
 def alg_bytes(info: dict, kernel: str) -> float:
     """Algorithmic HBM bytes of one launch group of `kernel` for one matvec
-    (each grid value read or written once; see the design notes)."""
+    (each grid value of the active box or of the kept modes read or written
+    once, plus the point rows and vectors)."""
     d = info["d"]
     s = 8 if info["precision"] == 0 else 4
     cs = 2 * s

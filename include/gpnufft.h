@@ -136,7 +136,8 @@ int gp_opts_init(gp_opts* opts);
  * dimensions (eq:boldK).  pts (n x d), sigma (n), l (n): device fp64.
  * nu > 0 (INFINITY = squared exponential), eta >= 0 noise s.d. (eq:gprsolve),
  * tol > 0 target accuracy for the approximation (section 5 / section 6).
- * Parameter choices: see gp_plan_params and the design notes.  On success
+ * Parameter choices are reported in gp_plan_params and can be computed
+ * without device data by gp_plan_rules.  On success
  * *out owns all device memory it needs; release it with gp_plan_destroy. */
 int gp_plan(int d, int64_t n, const double* pts, const double* sigma, const double* l,
             double nu, double eta, double tol, const gp_opts* opts, gp_plan_t* out);

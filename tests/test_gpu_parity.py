@@ -1,6 +1,6 @@
 """GPU parity: the HIP path (through the C ABI) against the CPU oracle.
 
-Bar (spec tolerances): relative 2-norm error of the matvec <= 1e-6 in the
+Bar: relative 2-norm error of the matvec <= 1e-6 in the
 fp64 path and <= 2e-4 in the fp32-bulk path against the oracle's K~ with the
 same parameters; CG solutions within 1e-6 of the Cholesky solution.
 """
