@@ -674,11 +674,15 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(
 // points' rows are staged once, and each thread keeps its items' partial sums
 // over all pairs in registers.  Items are (row group, point), row group
 // fastest; the RG lanes of a point combine by xor shuffles at the end, so the
-// order of every sum is fixed.
+// order of every sum is fixed.  The next pair's tile is loaded into registers
+// while the current pair is computed (the kernel is otherwise latency-bound:
+// 1.71 -> 0.88 ms at d=2 N=1e6 fp64).
 constexpr int kPB2 = 128;                                   // points staged per batch
 constexpr int kNI2 = (kPB2 * kRG + kThreads - 1) / kThreads;  // items per thread
 
-template <typename T>
+constexpr int kTE = 8;  // tile cells per thread kept in flight by the pipelined variant
+
+template <typename T, bool PIPE>
 __global__ __launch_bounds__(kThreads) void interp_super_kernel(
     NuArgs a, const typename V2<T>::type* __restrict__ grid, const int* __restrict__ cell,
     const T* __restrict__ pw, int rs, const int* __restrict__ bin_start,
@@ -728,16 +732,48 @@ __global__ __launch_bounds__(kThreads) void interp_super_kernel(
 #pragma unroll
     for (int k = 0; k < kNI2; ++k) part[k] = 0.0;
     const int nitems = np * RG;
+    const int ucells = pc0 * pc1;
+    // PIPE: the next pair's tile is loaded into registers while this pair is
+    // computed, and stored to LDS after the barrier (ucells <= kTE kThreads)
+    V nxt[PIPE ? kTE : 1];
+    auto load_tile = [&](int g) {
+#pragma unroll
+      for (int j = 0; j < (PIPE ? kTE : 1); ++j) {
+        const int e = threadIdx.x + j * kThreads;
+        V v = V{T(0), T(0)};
+        if (e < ucells) {
+          const int l1 = e / pc0, l0 = e - l1 * pc0;
+          const int c0 = t00 + l0, c1 = t01 + l1;
+          if (c0 < a.na[0] && c1 < a.na[1])
+            v = grid[(int64_t)g * a.pair_stride + a.grid_off + (int64_t)c0 * a.gstride[0] +
+                     (int64_t)c1 * a.gstride[1]];
+        }
+        nxt[j] = v;
+      }
+    };
+    if (PIPE) load_tile(0);
     for (int g = 0; g < a.npair; ++g) {
       __syncthreads();  // records staged / previous pair's tile no longer read
-      for (int e = threadIdx.x; e < pc0 * pc1; e += kThreads) {
-        const int l1 = e / pc0, l0 = e - l1 * pc0;
-        const int c0 = t00 + l0, c1 = t01 + l1;
-        V v = V{T(0), T(0)};
-        if (c0 < a.na[0] && c1 < a.na[1])
-          v = grid[(int64_t)g * a.pair_stride + a.grid_off + (int64_t)c0 * a.gstride[0] +
-                   (int64_t)c1 * a.gstride[1]];
-        tile[l1 * ps0 + l0] = v;
+      if (PIPE) {
+#pragma unroll
+        for (int j = 0; j < (PIPE ? kTE : 1); ++j) {
+          const int e = threadIdx.x + j * kThreads;
+          if (e < ucells) {
+            const int l1 = e / pc0, l0 = e - l1 * pc0;
+            tile[l1 * ps0 + l0] = nxt[j];
+          }
+        }
+        if (g + 1 < a.npair) load_tile(g + 1);
+      } else {
+        for (int e = threadIdx.x; e < ucells; e += kThreads) {
+          const int l1 = e / pc0, l0 = e - l1 * pc0;
+          const int c0 = t00 + l0, c1 = t01 + l1;
+          V v = V{T(0), T(0)};
+          if (c0 < a.na[0] && c1 < a.na[1])
+            v = grid[(int64_t)g * a.pair_stride + a.grid_off + (int64_t)c0 * a.gstride[0] +
+                     (int64_t)c1 * a.gstride[1]];
+          tile[l1 * ps0 + l0] = v;
+        }
       }
       __syncthreads();
 #pragma unroll
@@ -991,7 +1027,11 @@ void launch_interp_super(Plan* P, const Records& R, const double* xs, double* ys
   NuArgs a = nu_args(P, R);
   a.add_noise = add_noise;
   if (R.n_in_work2 == 0) return;
-  hipLaunchKernelGGL((interp_super_kernel<T>), dim3((unsigned)R.n_in_work2), dim3(kThreads),
+  const int ucells = (2 * P->tile[0] + P->w - 1) * (2 * P->tile[1] + P->w - 1);
+  // software-pipelined tile loads when a pair's tile fits kTE cells per thread
+  const bool pipe = ucells <= kTE * kThreads;
+  auto kern = pipe ? interp_super_kernel<T, true> : interp_super_kernel<T, false>;
+  hipLaunchKernelGGL(kern, dim3((unsigned)R.n_in_work2), dim3(kThreads),
                      interp_super_smem<T>(P, R.rs), P->stream, a,
                      P->gridA.as<typename V2<T>::type>(), R.cell.as<int>(), R.pw.as<T>(), R.rs,
                      R.bin_start.as<int>(), R.in_work2.as<int4>(), xs, ys);
