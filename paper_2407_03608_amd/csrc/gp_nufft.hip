@@ -126,44 +126,62 @@ __global__ __launch_bounds__(kThreads) void spread_owner_kernel(
   const int wko = D * w + 2 * a.g0;
   int nsrc_tot = 1;
   for (int r = 0; r < D; ++r) nsrc_tot *= a.nsrc;
-  int pos = 0;  // start of the current source bin in the tile's source sequence
-  for (int sb = 0; sb < nsrc_tot && pos < src_hi; ++sb) {
+  // The tile's source sequence: its source bins in order (offset q along each
+  // dimension, first dimension fastest; bins before the grid start skipped),
+  // concatenated.  Thread sb < nsrc_tot records bin sb's range and the
+  // dimensions along which it lies before the tile.
+  int* s_sb0 = s_np + 1;                  // [nsrc_tot] first sorted index
+  int* s_soff = s_sb0 + nsrc_tot;         // [nsrc_tot + 1] offsets in the sequence
+  int* s_smask = s_soff + nsrc_tot + 1;   // [nsrc_tot] offset-dimension mask
+  for (int sb = threadIdx.x; sb < nsrc_tot; sb += kThreads) {
     int64_t bin = 0, mul = 1;
     bool ok = true;
-    int q = sb;
+    int q = sb, mask = 0;
     for (int r = 0; r < D; ++r) {
-      int br = tcoord[r] - (q % a.nsrc);
+      const int dq = q % a.nsrc;
+      const int br = tcoord[r] - dq;
       q /= a.nsrc;
+      if (dq) mask |= 1 << r;
       if (br < 0) ok = false;
       bin += (int64_t)br * mul;
       mul *= a.nbins[r];
     }
-    if (!ok) continue;
-    const int b0 = bin_start[bin], cnt = bin_start[bin + 1] - b0;
-    const int p0 = b0 + max(src_lo - pos, 0), p1 = b0 + min(src_hi - pos, cnt);
-    pos += cnt;
-    // Along a dimension where this source bin lies before the tile, a point
-    // reaches the tile only if the last cell of its window does: wave 0
-    // filters each batch of candidates and compacts the survivors (ballot),
-    // so only they are staged and tested by every thread.
-    int offmask = 0;
+    const int b0 = ok ? bin_start[bin] : 0;
+    s_sb0[sb] = b0;
+    s_soff[sb + 1] = ok ? bin_start[bin + 1] - b0 : 0;  // count, summed below
+    s_smask[sb] = mask;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    s_soff[0] = 0;
+    for (int sb = 0; sb < nsrc_tot; ++sb) s_soff[sb + 1] += s_soff[sb];
+  }
+  __syncthreads();
+  const int seq_lo = max(src_lo, 0), seq_hi = min(src_hi, s_soff[nsrc_tot]);
+  // Windows of kPB consecutive candidates of the sequence.  Along a dimension
+  // where a candidate's bin lies before the tile, the point reaches the tile
+  // only if the last cell of its window does: wave 0 filters each window and
+  // compacts the survivors (ballot), so only they are staged and tested by
+  // every thread.  The order of the survivors is the sequence order.
+  for (int base = seq_lo; base < seq_hi; base += kPB) {
     {
-      int q2 = sb;
-      for (int r = 0; r < D; ++r) {
-        if (q2 % a.nsrc) offmask |= 1 << r;
-        q2 /= a.nsrc;
-      }
-    }
-    for (int pb = p0; pb < p1; pb += kPB) {
-      const int nc = min(kPB, p1 - pb);
+      const int nc = min(kPB, seq_hi - base);
       __syncthreads();
       if (threadIdx.x < kPB) {  // wave 0 (kPB is the wavefront size)
         bool keep = (int)threadIdx.x < nc;
-        if (keep && offmask)
-          for (int r = 0; r < D; ++r)
-            if ((offmask >> r) & 1) keep = keep && cell[r * a.n + pb + threadIdx.x] + w - 1 >= t0[r];
+        int idx = 0;
+        if (keep) {
+          const int qpos = base + threadIdx.x;
+          int sb = 0;
+          while (qpos >= s_soff[sb + 1]) ++sb;
+          idx = s_sb0[sb] + (qpos - s_soff[sb]);
+          const int mask = s_smask[sb];
+          if (mask)
+            for (int r = 0; r < D; ++r)
+              if ((mask >> r) & 1) keep = keep && cell[r * a.n + idx] + w - 1 >= t0[r];
+        }
         const unsigned long long m = __ballot(keep);
-        if (keep) s_map[__popcll(m & ((1ull << threadIdx.x) - 1ull))] = pb + threadIdx.x;
+        if (keep) s_map[__popcll(m & ((1ull << threadIdx.x) - 1ull))] = idx;
         if (threadIdx.x == 0) *s_np = __popcll(m);
       }
       __syncthreads();
@@ -878,7 +896,10 @@ NuArgs nu_args(const Plan* P, const Records& R) {
 template <typename T>
 size_t spread_owner_smem(const Plan* P, int rs) {
   static_assert(kPB == 64, "the spread pre-filter compacts one batch per wavefront");
-  return kPB * (lds_stride(rs) + 1) * sizeof(T) + (kPB * P->d + kPB + 1) * sizeof(int) + 16;
+  int nsrc_tot = 1;
+  for (int r = 0; r < P->d; ++r) nsrc_tot *= P->nsrc;
+  return kPB * (lds_stride(rs) + 1) * sizeof(T) + (kPB * P->d + kPB + 1) * sizeof(int) +
+         (3 * (size_t)nsrc_tot + 1) * sizeof(int) + 16;
 }
 
 template <typename T, int D, int CPT>
