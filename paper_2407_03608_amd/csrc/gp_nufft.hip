@@ -336,7 +336,10 @@ __global__ __launch_bounds__(kSubThreads) void spread_sub_kernel(
   const int wko = D * w + 2 * a.g0;
   int nsrc_tot = 1;
   for (int r = 0; r < D; ++r) nsrc_tot *= a.nsrc;
-  for (int sb = 0; sb < nsrc_tot; ++sb) {
+  // the concatenated source bins, as in spread_owner_kernel
+  int* s_sb0 = s_np + 1;           // [nsrc_tot]
+  int* s_soff = s_sb0 + nsrc_tot;  // [nsrc_tot + 1]
+  for (int sb = threadIdx.x; sb < nsrc_tot; sb += kSubThreads) {
     int64_t b = 0, mul = 1;
     bool ok = true;
     int q = sb;
@@ -347,19 +350,35 @@ __global__ __launch_bounds__(kSubThreads) void spread_sub_kernel(
       b += (int64_t)br * mul;
       mul *= a.nbins[r];
     }
-    if (!ok) continue;
-    const int p0 = bin_start[b], p1 = bin_start[b + 1];
-    for (int pb = p0; pb < p1; pb += kPB) {
-      const int nc = min(kPB, p1 - pb);
+    const int b0 = ok ? bin_start[b] : 0;
+    s_sb0[sb] = b0;
+    s_soff[sb + 1] = ok ? bin_start[b + 1] - b0 : 0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    s_soff[0] = 0;
+    for (int sb = 0; sb < nsrc_tot; ++sb) s_soff[sb + 1] += s_soff[sb];
+  }
+  __syncthreads();
+  const int seq_hi = s_soff[nsrc_tot];
+  for (int base = 0; base < seq_hi; base += kPB) {
+    {
+      const int nc = min(kPB, seq_hi - base);
       __syncthreads();
       bool keep = (int)threadIdx.x < nc;
-      if (keep)
+      int idx = 0;
+      if (keep) {
+        const int qpos = base + threadIdx.x;
+        int sb = 0;
+        while (qpos >= s_soff[sb + 1]) ++sb;
+        idx = s_sb0[sb] + (qpos - s_soff[sb]);
         for (int r = 0; r < D; ++r) {
-          const int cr = cell[r * a.n + pb + threadIdx.x];
+          const int cr = cell[r * a.n + idx];
           keep = keep && cr + w - 1 >= s0[r] && cr < s0[r] + st;
         }
+      }
       const unsigned long long m = __ballot(keep);
-      if (keep) s_map[__popcll(m & ((1ull << threadIdx.x) - 1ull))] = pb + threadIdx.x;
+      if (keep) s_map[__popcll(m & ((1ull << threadIdx.x) - 1ull))] = idx;
       const int np = __popcll(m);
       __syncthreads();
       if (np == 0) continue;
