@@ -85,8 +85,8 @@ struct Records {
   //  sp_red   int4 {tile, slot0, count, 0}: grid tile = sum of its partials,
   //           added in slot order
   //  in_work  int4 {bin, p_lo, p_hi, 0}: interpolate sorted points [p_lo, p_hi)
-  //  in_work2 int4 {super-bin, lo, hi, 0} (d = 2): interpolate positions
-  //           [lo, hi) of the points of a 2x2 block of bins (its two bin rows
+  //  in_work2 int4 {super-bin, lo, hi, 0} (d >= 2): interpolate positions
+  //           [lo, hi) of the points of a 2x2(x1) block of bins (its two bin rows
   //           in order, each a contiguous range of the sorted points)
   DevBuf sp_work, sp_red, in_work, in_work2, part;
   int64_t n_sp_work = 0, n_sp_red = 0, n_in_work = 0, n_in_work2 = 0, n_slots = 0;

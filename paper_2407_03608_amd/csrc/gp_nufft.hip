@@ -705,7 +705,7 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(
 }
 
 // ------------------------------------------------- interp (2x2 super-tile) ----
-// d = 2.  One workgroup per chunk of the points of a 2x2 block of bins: the
+// d = 2, 3.  One workgroup per chunk of the points of a 2x2(x1) block of bins: the
 // block's cells plus the (w-1) halo are staged in LDS for one grid pair at a
 // time (halo overhead (2t+w-1)^2/(2t)^2 instead of (t+w-1)^2/t^2 per bin), the
 // points' rows are staged once, and each thread keeps its items' partial sums
@@ -717,9 +717,12 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(
 constexpr int kPB2 = 128;                                   // points staged per batch
 constexpr int kNI2 = (kPB2 * kRG + kThreads - 1) / kThreads;  // items per thread
 
-constexpr int kTE = 8;  // tile cells per thread kept in flight by the pipelined variant
+// tile cells per thread kept in flight by the pipelined variant (a d=3 block
+// of 2x2x1 bins of 8^3 cells with w = 5 has 20 x 20 x 12 = 4800 cells)
+template <int D>
+constexpr int kTE = D > 2 ? 20 : 8;
 
-template <typename T, bool PIPE>
+template <typename T, bool PIPE, int D>
 __global__ __launch_bounds__(kThreads) void interp_super_kernel(
     NuArgs a, const typename V2<T>::type* __restrict__ grid, const int* __restrict__ cell,
     const T* __restrict__ pw, int rs, const int* __restrict__ bin_start,
@@ -727,29 +730,32 @@ __global__ __launch_bounds__(kThreads) void interp_super_kernel(
   using V = typename V2<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
   const int w = a.w;
-  const int st0 = 2 * a.tile[0], st1 = 2 * a.tile[1];
-  const int pc0 = st0 + w - 1, pc1 = st1 + w - 1;
+  // blocks of 2 x 2 (x 1) bins: the first two dimensions doubled
+  const int st0 = 2 * a.tile[0], st1 = 2 * a.tile[1], st2 = D > 2 ? a.tile[2] : 1;
+  const int pc0 = st0 + w - 1, pc1 = st1 + w - 1, pc2 = D > 2 ? st2 + w - 1 : 1;
   const int ps0 = pc0 | 1;  // odd row stride: the RG lanes of a point hit different banks
   const int ls = lds_stride(rs);
-  V* tile = reinterpret_cast<V*>(smem);                          // [pc1][ps0]
-  T* s_rec = reinterpret_cast<T*>(tile + (size_t)ps0 * pc1);     // [kPB2][ls]
-  int* s_cell = reinterpret_cast<int*>(s_rec + kPB2 * ls);       // [kPB2][2]
-  int* s_idx = s_cell + 2 * kPB2;                                 // [kPB2] sorted index
+  V* tile = reinterpret_cast<V*>(smem);                              // [pc2][pc1][ps0]
+  T* s_rec = reinterpret_cast<T*>(tile + (size_t)ps0 * pc1 * pc2);   // [kPB2][ls]
+  int* s_cell = reinterpret_cast<int*>(s_rec + kPB2 * ls);           // [kPB2][D]
+  int* s_idx = s_cell + D * kPB2;                                     // [kPB2] sorted index
 
   const int4 wk = work[blockIdx.x];
-  const int nsb0 = (a.nbins[0] + 1) / 2;
-  const int sx = wk.x % nsb0, sy = wk.x / nsb0;
-  const int t00 = sx * st0, t01 = sy * st1;
+  const int nsb0 = (a.nbins[0] + 1) / 2, nsb1 = (a.nbins[1] + 1) / 2;
+  const int sx = wk.x % nsb0, sy = (wk.x / nsb0) % nsb1, sz = D > 2 ? wk.x / (nsb0 * nsb1) : 0;
+  const int t00 = sx * st0, t01 = sy * st1, t02 = sz * st2;
   const int bx0 = 2 * sx, bx1 = min(2 * sx + 1, a.nbins[0] - 1);
   int r_lo[2] = {0, 0}, r_len0 = 0;
   for (int q = 0; q < 2; ++q) {
     const int by = 2 * sy + q;
     if (by >= a.nbins[1]) break;
-    r_lo[q] = bin_start[by * a.nbins[0] + bx0];
-    if (q == 0) r_len0 = bin_start[by * a.nbins[0] + bx1 + 1] - r_lo[0];
+    const int64_t rowbin = ((int64_t)sz * a.nbins[1] + by) * a.nbins[0];
+    r_lo[q] = bin_start[rowbin + bx0];
+    if (q == 0) r_len0 = bin_start[rowbin + bx1 + 1] - r_lo[0];
   }
-  const int RG = w >= kRG ? kRG : (w >= 2 ? 2 : 1);  // power of two; kThreads % RG == 0
-  const int wko = 2 * w;
+  const int cellsw = D > 2 ? w * w : w;  // window rows per point
+  const int RG = cellsw >= kRG ? kRG : (cellsw >= 2 ? 2 : 1);  // power of two; kThreads % RG == 0
+  const int wko = D * w;
   for (int pos = wk.y; pos < wk.z; pos += kPB2) {
     const int np = min(kPB2, wk.z - pos);
     __syncthreads();
@@ -757,8 +763,9 @@ __global__ __launch_bounds__(kThreads) void interp_super_kernel(
       const int q = pos + e;
       const int idx = q < r_len0 ? r_lo[0] + q : r_lo[1] + (q - r_len0);
       s_idx[e] = idx;
-      s_cell[2 * e] = cell[idx] - t00;
-      s_cell[2 * e + 1] = cell[a.n + idx] - t01;
+      s_cell[D * e] = cell[idx] - t00;
+      s_cell[D * e + 1] = cell[a.n + idx] - t01;
+      if (D > 2) s_cell[D * e + 2] = cell[2 * a.n + idx] - t02;
     }
     __syncthreads();
     for (int e = threadIdx.x; e < np * rs; e += kThreads) {
@@ -769,21 +776,22 @@ __global__ __launch_bounds__(kThreads) void interp_super_kernel(
 #pragma unroll
     for (int k = 0; k < kNI2; ++k) part[k] = 0.0;
     const int nitems = np * RG;
-    const int ucells = pc0 * pc1;
+    const int ucells = pc0 * pc1 * pc2;
     // PIPE: the next pair's tile is loaded into registers while this pair is
     // computed, and stored to LDS after the barrier (ucells <= kTE kThreads)
-    V nxt[PIPE ? kTE : 1];
+    V nxt[PIPE ? kTE<D> : 1];
     auto load_tile = [&](int g) {
 #pragma unroll
-      for (int j = 0; j < (PIPE ? kTE : 1); ++j) {
+      for (int j = 0; j < (PIPE ? kTE<D> : 1); ++j) {
         const int e = threadIdx.x + j * kThreads;
         V v = V{T(0), T(0)};
         if (e < ucells) {
-          const int l1 = e / pc0, l0 = e - l1 * pc0;
-          const int c0 = t00 + l0, c1 = t01 + l1;
-          if (c0 < a.na[0] && c1 < a.na[1])
+          const int l12 = e / pc0, l0 = e - l12 * pc0;
+          const int l1 = D > 2 ? l12 % pc1 : l12, l2 = D > 2 ? l12 / pc1 : 0;
+          const int c0 = t00 + l0, c1 = t01 + l1, c2 = t02 + l2;
+          if (c0 < a.na[0] && c1 < a.na[1] && (D < 3 || c2 < a.na[2]))
             v = grid[(int64_t)g * a.pair_stride + a.grid_off + (int64_t)c0 * a.gstride[0] +
-                     (int64_t)c1 * a.gstride[1]];
+                     (int64_t)c1 * a.gstride[1] + (D > 2 ? (int64_t)c2 * a.gstride[2] : 0)];
         }
         nxt[j] = v;
       }
@@ -793,23 +801,30 @@ __global__ __launch_bounds__(kThreads) void interp_super_kernel(
       __syncthreads();  // records staged / previous pair's tile no longer read
       if (PIPE) {
 #pragma unroll
-        for (int j = 0; j < (PIPE ? kTE : 1); ++j) {
+        for (int j = 0; j < (PIPE ? kTE<D> : 1); ++j) {
           const int e = threadIdx.x + j * kThreads;
           if (e < ucells) {
-            const int l1 = e / pc0, l0 = e - l1 * pc0;
-            tile[l1 * ps0 + l0] = nxt[j];
+            const int l12 = e / pc0, l0 = e - l12 * pc0;
+            tile[l12 * ps0 + l0] = nxt[j];
           }
         }
         if (g + 1 < a.npair) load_tile(g + 1);
       } else {
+        // cell (l0, l1, l2) of the thread's e, stepped by kThreads = s12 rows + s0 cells
+        const int s12 = kThreads / pc0, s0 = kThreads - s12 * pc0;
+        int l0 = threadIdx.x % pc0, l1 = threadIdx.x / pc0, l2 = 0;
+        while (l1 >= pc1) { l1 -= pc1; ++l2; }
         for (int e = threadIdx.x; e < ucells; e += kThreads) {
-          const int l1 = e / pc0, l0 = e - l1 * pc0;
-          const int c0 = t00 + l0, c1 = t01 + l1;
+          const int c0 = t00 + l0, c1 = t01 + l1, c2 = t02 + l2;
           V v = V{T(0), T(0)};
-          if (c0 < a.na[0] && c1 < a.na[1])
+          if (c0 < a.na[0] && c1 < a.na[1] && (D < 3 || c2 < a.na[2]))
             v = grid[(int64_t)g * a.pair_stride + a.grid_off + (int64_t)c0 * a.gstride[0] +
-                     (int64_t)c1 * a.gstride[1]];
-          tile[l1 * ps0 + l0] = v;
+                     (int64_t)c1 * a.gstride[1] + (D > 2 ? (int64_t)c2 * a.gstride[2] : 0)];
+          tile[(l2 * pc1 + l1) * ps0 + l0] = v;
+          l0 += s0;
+          l1 += s12;
+          if (l0 >= pc0) { l0 -= pc0; ++l1; }
+          while (l1 >= pc1) { l1 -= pc1; ++l2; }
         }
       }
       __syncthreads();
@@ -819,10 +834,12 @@ __global__ __launch_bounds__(kThreads) void interp_super_kernel(
         if (it < nitems) {
           const int rg = it % RG, p = it / RG;
           const T* pr = s_rec + p * ls;
-          const int o0 = s_cell[2 * p], o1 = s_cell[2 * p + 1];
+          const int o0 = s_cell[D * p], o1 = s_cell[D * p + 1], o2 = D > 2 ? s_cell[D * p + 2] : 0;
           double acc = 0.0;
-          for (int row = rg; row < w; row += RG) {
-            const V* tr = tile + (o1 + row) * ps0 + o0;
+          // window row (q1, q2) of row index q2 w + q1, stepped by RG < w
+          int q1 = D > 2 ? (rg < w ? rg : rg - w) : rg, q2 = D > 2 && rg >= w ? 1 : 0;
+          for (int row = rg; row < cellsw; row += RG) {
+            const V* tr = tile + ((o2 + q2) * pc1 + (o1 + q1)) * ps0 + o0;
             T rx = 0, ry = 0;
             for (int q0 = 0; q0 < w; ++q0) {
               const T ps = pr[q0];
@@ -830,8 +847,13 @@ __global__ __launch_bounds__(kThreads) void interp_super_kernel(
               rx += ps * gv.x;
               ry += ps * gv.y;
             }
-            acc += (double)pr[w + row] * ((double)pr[wko + 2 * g] * (double)rx +
+            const T wv = D > 2 ? pr[w + q1] * pr[2 * w + q2] : pr[w + row];
+            acc += (double)wv * ((double)pr[wko + 2 * g] * (double)rx +
                                           (double)pr[wko + 2 * g + 1] * (double)ry);
+            q1 += RG;
+            if (D > 2) {
+              while (q1 >= w) { q1 -= w; ++q2; }
+            }
           }
           part[k] += acc;
         }
@@ -1057,8 +1079,9 @@ void launch_interp_gather(Plan* P, const Records& R, const double* xs, double* y
 template <typename T>
 size_t interp_super_smem(const Plan* P, int rs) {
   const size_t pc0 = (size_t)(2 * P->tile[0] + P->w - 1), pc1 = (size_t)(2 * P->tile[1] + P->w - 1);
-  return (pc0 | 1) * pc1 * sizeof(typename V2<T>::type) + (size_t)kPB2 * lds_stride(rs) * sizeof(T) +
-         3 * kPB2 * sizeof(int) + 16;
+  const size_t pc2 = P->d > 2 ? (size_t)(P->tile[2] + P->w - 1) : 1;
+  return (pc0 | 1) * pc1 * pc2 * sizeof(typename V2<T>::type) +
+         (size_t)kPB2 * lds_stride(rs) * sizeof(T) + (P->d + 1) * kPB2 * sizeof(int) + 16;
 }
 
 template <typename T>
@@ -1067,10 +1090,12 @@ void launch_interp_super(Plan* P, const Records& R, const double* xs, double* ys
   NuArgs a = nu_args(P, R);
   a.add_noise = add_noise;
   if (R.n_in_work2 == 0) return;
-  const int ucells = (2 * P->tile[0] + P->w - 1) * (2 * P->tile[1] + P->w - 1);
+  const int ucells = (2 * P->tile[0] + P->w - 1) * (2 * P->tile[1] + P->w - 1) *
+                     (P->d > 2 ? P->tile[2] + P->w - 1 : 1);
   // software-pipelined tile loads when a pair's tile fits kTE cells per thread
-  const bool pipe = ucells <= kTE * kThreads;
-  auto kern = pipe ? interp_super_kernel<T, true> : interp_super_kernel<T, false>;
+  const bool pipe = ucells <= (P->d > 2 ? kTE<3> : kTE<2>) * kThreads;
+  auto kern = P->d == 2 ? (pipe ? interp_super_kernel<T, true, 2> : interp_super_kernel<T, false, 2>)
+                        : (pipe ? interp_super_kernel<T, true, 3> : interp_super_kernel<T, false, 3>);
   hipLaunchKernelGGL(kern, dim3((unsigned)R.n_in_work2), dim3(kThreads),
                      interp_super_smem<T>(P, R.rs), P->stream, a,
                      P->gridA.as<typename V2<T>::type>(), R.cell.as<int>(), R.pw.as<T>(), R.rs,
@@ -1080,7 +1105,7 @@ void launch_interp_super(Plan* P, const Records& R, const double* xs, double* ys
 
 template <typename T>
 void interp_dispatch(Plan* P, const Records& R, const double* xs, double* ys, int add_noise) {
-  if (P->interp_mode == 0 && P->d == 2 && interp_super_smem<T>(P, R.rs) <= kSmemCap) {
+  if (P->interp_mode == 0 && P->d >= 2 && interp_super_smem<T>(P, R.rs) <= kSmemCap) {
     launch_interp_super<T>(P, R, xs, ys, add_noise);
     return;
   }

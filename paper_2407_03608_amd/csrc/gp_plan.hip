@@ -490,8 +490,9 @@ size_t work_list_bound_bytes(const Plan* P, int64_t n, size_t cs) {
   const int64_t items = P->n_bins + ts / qs + 1;
   const int64_t qi = chunk_size(n, P->n_bins, kMinInterpChunk);
   const int64_t iitems = P->n_bins + n / qi + 1;
-  const int64_t nsup = P->n_bins / 4 + 2 * P->nbins[0] + 2;
-  const int64_t sitems = P->d == 2 ? nsup + n / chunk_size(n, nsup, kMinSuperChunk) + 1 : 0;
+  const int64_t nsup = (int64_t)((P->nbins[0] + 1) / 2) * ((P->nbins[1] + 1) / 2) *
+                       (P->d > 2 ? P->nbins[2] : 1);
+  const int64_t sitems = P->d >= 2 ? nsup + n / chunk_size(n, nsup, kMinSuperChunk) + 1 : 0;
   return (size_t)(2 * items + iitems + sitems) * 16 + (size_t)slots * tcells * slot_pairs(P) * cs;
 }
 
@@ -557,23 +558,27 @@ static void build_work_lists(Plan* P, Records& R, const std::vector<int>& start,
   // 2x2 super-bins (d = 2): the points of bin rows 2sy and 2sy+1, bins
   // 2sx..2sx+1 of each, in that order
   std::vector<int> inw2;
-  if (d == 2) {
+  if (d >= 2) {
     const int nsb0 = (P->nbins[0] + 1) / 2, nsb1 = (P->nbins[1] + 1) / 2;
-    const int64_t q2 = chunk_size(R.n, (int64_t)nsb0 * nsb1, kMinSuperChunk);
-    for (int sy = 0; sy < nsb1; ++sy)
-      for (int sx = 0; sx < nsb0; ++sx) {
-        const int bx0 = 2 * sx, bx1 = std::min(2 * sx + 1, P->nbins[0] - 1);
-        int64_t cnt = 0;
-        for (int q = 0; q < 2; ++q) {
-          const int by = 2 * sy + q;
-          if (by >= P->nbins[1]) break;
-          cnt += start[(int64_t)by * P->nbins[0] + bx1 + 1] - start[(int64_t)by * P->nbins[0] + bx0];
+    const int nsb2 = d > 2 ? P->nbins[2] : 1;
+    const int64_t q2 = chunk_size(R.n, (int64_t)nsb0 * nsb1 * nsb2, kMinSuperChunk);
+    for (int sz = 0; sz < nsb2; ++sz)
+      for (int sy = 0; sy < nsb1; ++sy)
+        for (int sx = 0; sx < nsb0; ++sx) {
+          const int bx0 = 2 * sx, bx1 = std::min(2 * sx + 1, P->nbins[0] - 1);
+          int64_t cnt = 0;
+          for (int q = 0; q < 2; ++q) {
+            const int by = 2 * sy + q;
+            if (by >= P->nbins[1]) break;
+            const int64_t rowbin = ((int64_t)sz * P->nbins[1] + by) * P->nbins[0];
+            cnt += start[rowbin + bx1 + 1] - start[rowbin + bx0];
+          }
+          if (cnt == 0) continue;
+          const int64_t c = (cnt + q2 - 1) / q2;
+          const int sb = (sz * nsb1 + sy) * nsb0 + sx;
+          for (int64_t j = 0; j < c; ++j)
+            inw2.insert(inw2.end(), {sb, (int)(cnt * j / c), (int)(cnt * (j + 1) / c), 0});
         }
-        if (cnt == 0) continue;
-        const int64_t c = (cnt + q2 - 1) / q2;
-        for (int64_t j = 0; j < c; ++j)
-          inw2.insert(inw2.end(), {sy * nsb0 + sx, (int)(cnt * j / c), (int)(cnt * (j + 1) / c), 0});
-      }
   }
   hipStream_t s = P->stream;
   R.n_in_work2 = (int64_t)inw2.size() / 4;
