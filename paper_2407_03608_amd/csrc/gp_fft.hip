@@ -370,27 +370,27 @@ void launch_len(const FftPass& q, const void* in, void* out, const void* tw, hip
                        0, s, static_cast<const V*>(in), static_cast<V*>(out),
                        static_cast<const V*>(tw), static_cast<const V*>(q.tw4), p);
     GP_CHECK_LAUNCH();
-    return;
-  }
-  // Long strided (column) transforms: two columns per workgroup, so pairs of
-  // adjacent lanes read adjacent elements of one cache line.
-  if constexpr (B == 1 && L >= 6144) {
-    if (q.inner > 1) {
-      const int64_t nb2 = (p.ntrans + 1) / 2;
-      if (nb2 <= 0) return;
-      hipLaunchKernelGGL((fft_pass_kernel<T, L, EPT, 2>), dim3((unsigned)nb2), dim3(2 * (L / EPT)),
-                         0, s, static_cast<const V*>(in), static_cast<V*>(out),
-                         static_cast<const V*>(tw), static_cast<const V*>(q.tw4), p);
-      GP_CHECK_LAUNCH();
-      return;
+  } else {
+    // Long strided (column) transforms: two columns per workgroup, so pairs of
+    // adjacent lanes read adjacent elements of one cache line.
+    if constexpr (B == 1 && L >= 6144) {
+      if (q.inner > 1) {
+        const int64_t nb2 = (p.ntrans + 1) / 2;
+        if (nb2 <= 0) return;
+        hipLaunchKernelGGL((fft_pass_kernel<T, L, EPT, 2>), dim3((unsigned)nb2), dim3(2 * (L / EPT)),
+                           0, s, static_cast<const V*>(in), static_cast<V*>(out),
+                           static_cast<const V*>(tw), static_cast<const V*>(q.tw4), p);
+        GP_CHECK_LAUNCH();
+        return;
+      }
     }
+    const int64_t nblk = (p.ntrans + B - 1) / B;
+    if (nblk <= 0) return;
+    hipLaunchKernelGGL((fft_pass_kernel<T, L, EPT, B>), dim3((unsigned)nblk), dim3(B * (L / EPT)),
+                       0, s, static_cast<const V*>(in), static_cast<V*>(out),
+                       static_cast<const V*>(tw), static_cast<const V*>(q.tw4), p);
+    GP_CHECK_LAUNCH();
   }
-  const int64_t nblk = (p.ntrans + B - 1) / B;
-  if (nblk <= 0) return;
-  hipLaunchKernelGGL((fft_pass_kernel<T, L, EPT, B>), dim3((unsigned)nblk), dim3(B * (L / EPT)),
-                     0, s, static_cast<const V*>(in), static_cast<V*>(out),
-                     static_cast<const V*>(tw), static_cast<const V*>(q.tw4), p);
-  GP_CHECK_LAUNCH();
 }
 
 template <typename T>
