@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--tol64", type=float, default=1e-8)
     ap.add_argument("--tol32", type=float, default=1e-4)
     ap.add_argument("--solve", action="store_true", help="also time full CG solves to 1e-6")
+    ap.add_argument("--upsample", type=float, default=0.0,
+                    help="fine-grid oversampling of every plan, 1.25..2 (window widened to "
+                         "match); 0 = the library's automatic choice")
     ap.add_argument("--max-iter", type=int, default=20000)
     ap.add_argument("--inner-tol", type=float, default=3e-3)
     ap.add_argument("--replace-every", type=int, default=0,
@@ -179,7 +182,7 @@ def secondary_workloads(gp, torch, args):
     log("secondary: matern_1d")
     p1 = inputs.matern_1d()
     X, S, L, Y = (torch.as_tensor(v).to(dev) for v in (p1.x, p1.sigma, p1.l, p1.y))
-    P = gp.Plan(X, S, L, p1.nu, p1.eta, 1e-8)
+    P = gp.Plan(X, S, L, p1.nu, p1.eta, 1e-8, upsample=args.upsample)
     info = P.info()
     t, tm = time_path(gp, torch, P, Y, 200, 20)
     torch.cuda.synchronize()
@@ -192,7 +195,7 @@ def secondary_workloads(gp, torch, args):
         "ms_per_step": round(1e3 * t / 200, 4), "points_per_s": round(p1.n * 200 / t, 1),
         "solve_1e-8": {"seconds": round(ts, 4), "iters": ci["iters"], "status": ci["status"]},
         "kernels_ms": {k: round(v[1] / 200, 4) for k, v in tm.items() if v[0]},
-        "plan": {k: info[k] for k in ("n_sigma", "n_t", "dw", "M", "nf", "w")}}
+        "plan": {k: info[k] for k in ("n_sigma", "n_t", "dw", "M", "nf", "w", "upsample")}}
     P.close()
     del X, S, L, Y
     log("secondary: matern_3d fp32-bulk")
@@ -200,7 +203,7 @@ def secondary_workloads(gp, torch, args):
     X, S, L, Y = (torch.as_tensor(v).to(dev) for v in (p3.x, p3.sigma, p3.l, p3.y))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    P = gp.Plan(X, S, L, p3.nu, p3.eta, 1e-4, precision=gp.GP_FP32_BULK)
+    P = gp.Plan(X, S, L, p3.nu, p3.eta, 1e-4, precision=gp.GP_FP32_BULK, upsample=args.upsample)
     torch.cuda.synchronize()
     tp = time.perf_counter() - t0
     info = P.info()
@@ -213,7 +216,7 @@ def secondary_workloads(gp, torch, args):
         "ms_per_step": round(1e3 * t / steps, 4), "points_per_s": round(p3.n * steps / t, 1),
         "roofline": rf, "kernels_ms": {k: round(v[1] / steps, 4) for k, v in tm.items() if v[0]},
         "plan_seconds": round(tp, 3),
-        "plan": {k: info[k] for k in ("n_sigma", "n_t", "dw", "M", "nf", "w", "na", "n_pairs", "device_bytes")}}
+        "plan": {k: info[k] for k in ("n_sigma", "n_t", "dw", "M", "nf", "w", "upsample", "na", "n_pairs", "device_bytes")}}
     P.close()
     return out
 
@@ -378,7 +381,7 @@ def main():
 
     log("planning fp64")
     t0 = time.perf_counter()
-    P64 = gp.Plan(X, S, Lx, prob.nu, prob.eta, args.tol64)
+    P64 = gp.Plan(X, S, Lx, prob.nu, prob.eta, args.tol64, upsample=args.upsample)
     torch.cuda.synchronize()
     plan64_s = time.perf_counter() - t0
     info64 = P64.info()
@@ -387,7 +390,7 @@ def main():
     log("planning fp32-bulk")
     t0 = time.perf_counter()
     P32 = gp.Plan(X, S, Lx, prob.nu, prob.eta, args.tol32, precision=gp.GP_FP32_BULK,
-                  dw=info64["dw"], M=info64["M"])
+                  dw=info64["dw"], M=info64["M"], upsample=args.upsample)
     torch.cuda.synchronize()
     plan32_s = time.perf_counter() - t0
     info32 = P32.info()
@@ -425,7 +428,7 @@ def main():
         "data": "synthetic (seeded uniform points, closed-form scales)",
         "config": {"workload": "matern_2d: d=2, N=1e6 uniform [0,1]^2, nu=1/2, "
                                "sigma=exp(0.3 x1), l=0.02+0.02 x2, eta=0.05, fp64, tol 1e-8",
-                   "n": prob.n, "plan": {k: info64[k] for k in ("n_sigma", "n_t", "dw", "M", "nf", "w")}},
+                   "n": prob.n, "plan": {k: info64[k] for k in ("n_sigma", "n_t", "dw", "M", "nf", "w", "upsample")}},
         "roofline": rf64,
         "matvec_model_roofline": step_model(info64, ms64),
         "kernels_ms": kernels64,
@@ -433,7 +436,7 @@ def main():
         "fp32_bulk": {"value": round(prob.n * args.steps / t32, 1), "unit": "points/s",
                       "ms_per_step": round(ms32, 4), "roofline": rf32,
                       "matvec_model_roofline": step_model(info32, ms32), "kernels_ms": kernels32,
-                      "plan": {k: info32[k] for k in ("n_sigma", "n_t", "dw", "M", "nf", "w")},
+                      "plan": {k: info32[k] for k in ("n_sigma", "n_t", "dw", "M", "nf", "w", "upsample")},
                       "plan_seconds": round(plan32_s, 3),
                       "rel_diff_vs_fp64_matvec": diff},
     }

@@ -65,6 +65,15 @@ typedef struct gp_plan_s* gp_plan_t;
 typedef struct {
   int precision;            /* GP_FP64 (default) or GP_FP32_BULK */
   double nufft_tol;         /* spreading tolerance; 0 = tol (fp64) or max(tol, 1e-6) (fp32) */
+  double upsample;          /* fine-grid oversampling sigma: n_f >= sigma (2M+1), sigma in
+                               [1.25, 2]; 0 = automatic (1.25 for d = 2, where the FFT
+                               passes dominate; 2 for d = 1, 3).  The window follows the exponential-of-
+                               semicircle rules of Barnett, Magland and af Klinteberg (2019)
+                               for the oversampling reached, s = min(2, n_f / (2M+1)):
+                               s = 2: w = ceil(log10(1/tol)) + 1, beta = 2.30 w; s < 2:
+                               w = ceil(ln(10/tol) / (pi sqrt(1 - 1/s))),
+                               beta = 0.97 pi (1 - 1/(2 s)) w; w <= 16.  Outside the
+                               range: GP_EINVAL */
   int n_sigma;              /* Chebyshev degree N_sigma (eq:chebscheme); -1 = auto */
   int n_t;                  /* trapezoid intervals N_t (eq:dtscheme); -1 = auto; ignored for SE */
   double t_min, t_max;      /* t range; used only when n_t >= 1 is set */
@@ -107,6 +116,8 @@ typedef struct {
   int nf[3];                /* oversampled FFT length per dimension */
   int w;                    /* spreading window width (cells) */
   double beta;              /* exponential-of-semicircle shape parameter */
+  double upsample;          /* oversampling the window is sized for: min(2, n_f / (2M+1)),
+                               n_f being the smallest supported length >= requested sigma (2M+1) */
   double nufft_tol;
   int lo[3], na[3];         /* active sub-box of the fine grid (offset, length) */
   int tile[3];              /* spreading tile per dimension */

@@ -215,6 +215,7 @@ static void fill_params(const Plan& P, gp_plan_params* o) {
   o->scale = P.scale;
   o->w = P.w;
   o->beta = P.beta;
+  o->upsample = P.upsample;
   o->nufft_tol = P.nufft_tol;
   o->n_pairs = P.npair;
   o->device_bytes = P.device_bytes;

@@ -158,9 +158,11 @@ template <typename T, typename V, int R1, int R2> struct DftComp {
 };
 template <typename T, typename V> struct Dft<T, V, 16> : DftComp<T, V, 4, 4> {};
 template <typename T, typename V> struct Dft<T, V, 32> : DftComp<T, V, 8, 4> {};
+template <typename T, typename V> struct Dft<T, V, 24> : DftComp<T, V, 8, 3> {};
 
 constexpr int next_radix(int rem, int ept) {
   return (rem % 32 == 0 && ept % 32 == 0)   ? 32
+         : (rem % 24 == 0 && ept % 24 == 0) ? 24
          : (rem % 16 == 0 && ept % 16 == 0) ? 16
          : (rem % 8 == 0 && ept % 8 == 0)   ? 8
          : (rem % 4 == 0 && ept % 4 == 0)   ? 4
@@ -371,9 +373,10 @@ void launch_len(const FftPass& q, const void* in, void* out, const void* tw, hip
                        static_cast<const V*>(tw), static_cast<const V*>(q.tw4), p);
     GP_CHECK_LAUNCH();
   } else {
-    // Long strided (column) transforms: two columns per workgroup, so pairs of
-    // adjacent lanes read adjacent elements of one cache line.
-    if constexpr (B == 1 && L >= 6144) {
+    // Long fp32 strided (column) transforms: two columns per workgroup, so
+    // pairs of adjacent lanes read adjacent elements of one cache line (in
+    // fp64 the doubled LDS would leave one workgroup per CU).
+    if constexpr (B == 1 && L >= 6144 && sizeof(T) == 4) {
       if (q.inner > 1) {
         const int64_t nb2 = (p.ntrans + 1) / 2;
         if (nb2 <= 0) return;

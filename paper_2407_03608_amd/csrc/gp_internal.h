@@ -117,6 +117,7 @@ struct Plan {
   double nufft_tol = 0;
   int w = 0;
   double beta = 0;
+  double upsample = 2.0;
   int nf[3] = {1, 1, 1};
   int lo[3] = {0, 0, 0};
   int na[3] = {1, 1, 1};      // active-box length (multiple of tile)

@@ -18,6 +18,7 @@
 // the tile of their first window cell, so the sources are the 2^d (or more)
 // neighbouring bins), accumulates in LDS with LDS atomics and writes its tile
 // with plain coalesced stores.  No global atomics and no zero-fill pass.
+#include <algorithm>
 #include <climits>
 #include <cmath>
 #include <mutex>
@@ -986,16 +987,21 @@ void launch_spread(Plan* P, const Records& R, const double* xs) {
   }
 }
 
-// Dynamic LDS above 64 KB needs an explicit per-kernel opt-in.
+// Dynamic LDS above 64 KB needs an explicit opt-in for each kernel (each
+// instantiation: kernels of one signature are distinct functions).
 constexpr size_t kSmemBig = 150 * 1024;
 template <typename K>
 void allow_big_lds(K kernel) {
-  static std::once_flag once;
-  std::call_once(once, [&] {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmemBig);
-  });
+  static std::mutex mu;
+  static std::vector<const void*> done;
+  const void* f = reinterpret_cast<const void*>(kernel);
+  std::lock_guard<std::mutex> lk(mu);
+  if (std::find(done.begin(), done.end(), f) != done.end()) return;
+  GP_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmemBig));
+  done.push_back(f);
 }
+// The 2x2(x1)-bin interpolation takes up to 80 KB: two workgroups per CU.
+constexpr size_t kSmemSuper = 80 * 1024;
 
 template <typename T, int D>
 void launch_interp(Plan* P, const Records& R, const double* xs, double* ys, int add_noise) {
@@ -1096,6 +1102,7 @@ void launch_interp_super(Plan* P, const Records& R, const double* xs, double* ys
   const bool pipe = ucells <= (P->d > 2 ? kTE<3> : kTE<2>) * kThreads;
   auto kern = P->d == 2 ? (pipe ? interp_super_kernel<T, true, 2> : interp_super_kernel<T, false, 2>)
                         : (pipe ? interp_super_kernel<T, true, 3> : interp_super_kernel<T, false, 3>);
+  if (interp_super_smem<T>(P, R.rs) > kSmemCap) allow_big_lds(kern);
   hipLaunchKernelGGL(kern, dim3((unsigned)R.n_in_work2), dim3(kThreads),
                      interp_super_smem<T>(P, R.rs), P->stream, a,
                      P->gridA.as<typename V2<T>::type>(), R.cell.as<int>(), R.pw.as<T>(), R.rs,
@@ -1105,7 +1112,7 @@ void launch_interp_super(Plan* P, const Records& R, const double* xs, double* ys
 
 template <typename T>
 void interp_dispatch(Plan* P, const Records& R, const double* xs, double* ys, int add_noise) {
-  if (P->interp_mode == 0 && P->d >= 2 && interp_super_smem<T>(P, R.rs) <= kSmemCap) {
+  if (P->interp_mode == 0 && P->d >= 2 && interp_super_smem<T>(P, R.rs) <= kSmemSuper) {
     launch_interp_super<T>(P, R, xs, ys, add_noise);
     return;
   }

@@ -39,6 +39,7 @@ class GpOpts(ctypes.Structure):
     _fields_ = [
         ("precision", _c_i),
         ("nufft_tol", _c_d),
+        ("upsample", _c_d),
         ("n_sigma", _c_i),
         ("n_t", _c_i),
         ("t_min", _c_d),
@@ -81,6 +82,7 @@ class GpPlanParams(ctypes.Structure):
         ("nf", _c_i * 3),
         ("w", _c_i),
         ("beta", _c_d),
+        ("upsample", _c_d),
         ("nufft_tol", _c_d),
         ("lo", _c_i * 3),
         ("na", _c_i * 3),

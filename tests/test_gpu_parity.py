@@ -101,6 +101,24 @@ def test_matvec_fp32_vs_oracle(gp, d, n, M):
     _check_matvec(gp, prob, tol=1e-4, precision=1, bar=FP32_TOL, M=M)
 
 
+@pytest.mark.parametrize("d,n,M,prec,ups", [(1, 300, 150, 0, 1.25), (2, 700, 24, 0, 2.0),
+                                            (2, 600, 24, 1, 2.0), (3, 300, 8, 0, 1.25),
+                                            (3, 300, 8, 1, 1.25), (1, 257, 60, 0, 1.5)])
+def test_matvec_upsample_vs_oracle(gp, d, n, M, prec, ups):
+    """Oversampling other than the automatic choice (1.25 in 2-D, 2 in 1-D and
+    3-D): the grid and the exponential-of-semicircle window change together and
+    the result still meets the bar."""
+    prob = inputs.random_small(d, n, seed=60 + d, nu=1.5, lmin=0.08, lmax=0.2)
+    tol, bar = (1e-9, FP64_TOL) if prec == 0 else (1e-4, FP32_TOL)
+    P, info, *_ = _check_matvec(gp, prob, tol=tol, precision=prec, bar=bar, M=M, upsample=ups)
+    auto = _plan(gp, prob, tol=tol, precision=prec, M=M).info()
+    say(f"  nf {info['nf'][0]} (automatic {auto['nf'][0]}), w {info['w']} (automatic {auto['w']})")
+    if d != 2:   # below the automatic 2: coarser grid, wider window
+        assert info["nf"][0] < auto["nf"][0] and info["upsample"] < 2 and info["w"] > auto["w"]
+    else:        # 2 instead of the automatic 1.25: finer grid, narrower window
+        assert info["nf"][0] > auto["nf"][0] and info["w"] < auto["w"]
+
+
 def test_matvec_fourstep_1d(gp):
     """d = 1 with an oversampled grid longer than one FFT pass (four-step)."""
     prob = inputs.random_small(1, 200, seed=5, nu=1.5, lmin=0.01, lmax=0.03)

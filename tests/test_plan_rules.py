@@ -130,10 +130,18 @@ def test_window_grid_and_active_box(case):
     ntol = p["nufft_tol"]
     if prec == 1:
         assert ntol >= 1e-6
-    assert p["w"] == min(16, max(2, math.ceil(math.log10(1 / ntol)) + 1))
-    assert p["beta"] == pytest.approx(2.30 * p["w"])
-    nf = p["nf"][0]
-    assert nf >= 2 * (2 * p["M"] + 1)
+    # automatic oversampling: 1.25 asked in 2-D, 2 otherwise; the window is
+    # sized for the oversampling reached
+    nf, mc, s = p["nf"][0], 2 * p["M"] + 1, p["upsample"]
+    assert nf >= (1.25 if d == 2 else 2.0) * mc
+    assert s == pytest.approx(min(2.0, nf / mc))
+    if s >= 2:
+        assert p["w"] == min(16, max(2, math.ceil(math.log10(1 / ntol)) + 1))
+        assert p["beta"] == pytest.approx(2.30 * p["w"])
+    else:
+        w = min(16, max(2, math.ceil(math.log(10 / ntol) / (math.pi * math.sqrt(1 - 1 / s)))))
+        assert p["w"] == w
+        assert p["beta"] == pytest.approx(0.97 * math.pi * (1 - 0.5 / s) * w)
     m = nf
     while m % 2 == 0:
         m //= 2
@@ -147,6 +155,82 @@ def test_window_grid_and_active_box(case):
         # every window of a point in [-1, 1] starts and ends inside the box
         assert lo <= 0.5 * nf - nf * p["dw"] - 0.5 * p["w"]
         assert lo + na >= 0.5 * nf + nf * p["dw"] + 0.5 * p["w"]
+
+
+@pytest.mark.parametrize("case", CASES[:4], ids=IDS[:4])
+@pytest.mark.parametrize("ups", [1.25, 1.5])
+def test_upsampled_grid_and_window_rule(case, ups):
+    """Oversampling below 2: n_f is the smallest supported length >= ups (2M+1),
+    and the window is sized for the oversampling reached, s = min(2, n_f/(2M+1)),
+    by the exponential-of-semicircle rule w = ceil(ln(10/eps) / (pi sqrt(1 - 1/s))),
+    beta = 0.97 pi (1 - 1/(2s)) w."""
+    d = case[0]
+    p = _rules(case, upsample=ups)
+    base = _rules(case)
+    mc = 2 * p["M"] + 1
+    nf = p["nf"][0]
+    assert nf >= ups * mc and nf <= base["nf"][0]
+    s = min(2.0, nf / mc)
+    assert p["upsample"] == pytest.approx(s)
+    if s < 2:
+        w = min(16, max(2, math.ceil(math.log(10 / p["nufft_tol"]) / (math.pi * math.sqrt(1 - 1 / s)))))
+        assert p["w"] == w
+        assert p["beta"] == pytest.approx(0.97 * math.pi * (1 - 0.5 / s) * w)
+    assert p["w"] >= base["w"]
+    if d > 1:
+        # the grid length is one of the FFT's single-pass lengths
+        assert nf in [k << j for k in (1, 3) for j in range(3, 14) if (k << j) <= 8192]
+
+
+def _es_type2_error(M, nf, w, beta, seed=0, npts=1500):
+    """Relative 2-norm error of a 1-D type-2 NUFFT f(theta) = sum_{|k|<=M} c_k
+    e^{i k theta} done the usual way with the exponential-of-semicircle window
+    psi(z) = exp(beta (sqrt(1 - z^2) - 1)) of w cells on nf cells (deconvolve by
+    the window's Fourier transform, inverse FFT, interpolate), against the
+    direct sum.  Uses only (M, nf, w, beta)."""
+    rng = np.random.default_rng(seed)
+    k = np.arange(-M, M + 1)
+    c = rng.standard_normal(k.size) + 1j * rng.standard_normal(k.size)
+    h = 2 * np.pi / nf
+    z, gw = np.polynomial.legendre.leggauss(400)
+    psi = np.exp(beta * (np.sqrt(1 - z * z) - 1))
+    # psi_hat(k) = (1/h) int psi(2u/(w h)) e^{-iku} du
+    ph = 0.5 * w * (np.cos(np.outer(k, 0.5 * w * h * z)) @ (gw * psi))
+    arr = np.zeros(nf, complex)
+    arr[k % nf] = c / ph * (-1.0) ** k      # grid cell l sits at theta_l = l h - pi
+    G = nf * np.fft.ifft(arr)
+    theta = rng.uniform(-np.pi, np.pi, npts)
+    s = np.ceil((theta + np.pi) / h - 0.5 * w).astype(int)
+    f = np.zeros(npts, complex)
+    for q in range(w):
+        cell = s + q
+        u = (cell * h - np.pi - theta) / (0.5 * w * h)
+        wt = np.where(np.abs(u) <= 1, np.exp(beta * (np.sqrt(np.clip(1 - u * u, 0, None)) - 1)), 0.0)
+        f += wt * G[cell % nf]
+    ex = np.exp(1j * np.outer(theta, k)) @ c
+    return float(np.linalg.norm(f - ex) / np.linalg.norm(ex))
+
+
+@pytest.mark.parametrize("tol", [1e-4, 1e-8, 1e-11])
+@pytest.mark.parametrize("ups,M", [(2.0, 700), (1.5, 1000), (1.25, 700)])
+def test_window_rule_reaches_the_nufft_tolerance(tol, ups, M):
+    """The (w, beta, n_f) the plan picks give a type-2 NUFFT as accurate as
+    asked, checked by an independent numpy NUFFT against the direct sum; a
+    window two cells narrower misses it."""
+    p = gp.plan_rules(1, 1.5, 1e-6, 0.01, 0.02, M=M, nufft_tol=tol, upsample=ups)
+    if ups < 2:
+        assert p["upsample"] < 2
+    e = _es_type2_error(p["M"], p["nf"][0], p["w"], p["beta"])
+    assert e <= tol, (e, p["w"], p["nf"][0])
+    w2 = p["w"] - 2
+    assert _es_type2_error(p["M"], p["nf"][0], w2, p["beta"] * w2 / p["w"]) > tol
+
+
+@pytest.mark.parametrize("ups", [1.0, 1.2, 2.5])
+def test_upsample_outside_its_range_is_rejected(ups):
+    with pytest.raises(gp.GpError) as e:
+        gp.plan_rules(2, 1.5, 1e-6, 0.1, 0.2, upsample=ups)
+    assert e.value.code == gp.GP_EINVAL
 
 
 def test_rules_are_invariant_under_a_joint_scaling_of_box_and_lengths():
@@ -164,7 +248,7 @@ def test_fp32_plan_shares_dw_and_m_when_given():
     a = gp.plan_rules(2, 0.5, 1e-8, 0.02, 0.04)
     b = gp.plan_rules(2, 0.5, 1e-4, 0.02, 0.04, precision=gp.GP_FP32_BULK, dw=a["dw"], M=a["M"])
     assert b["dw"] == a["dw"] and b["M"] == a["M"] and b["nf"] == a["nf"]
-    assert b["w"] == 5 and b["n_sigma"] < a["n_sigma"] and b["n_t"] < a["n_t"]
+    assert b["w"] < a["w"] and b["n_sigma"] < a["n_sigma"] and b["n_t"] < a["n_t"]
 
 
 def test_overrides_are_taken_as_given():
