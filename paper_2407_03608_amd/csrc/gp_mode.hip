@@ -235,6 +235,60 @@ __global__ __launch_bounds__(kThreads) void mode_radial_kernel(
   }
 }
 
+// d = 1: the M+1 orthant points are too few to fill the chip one per thread,
+// so each point takes a group of NK lanes: lane j forms b_j, computes row j
+// of A b (terms in the order k = 0..NK-1, as the per-thread kernel adds them),
+// and lanes g < npair write the conjugate pair (n, -n) of grid g.
+template <typename T, int NK>
+__global__ __launch_bounds__(kThreads) void mode_radial_1d_kernel(
+    RadialArgs a, typename V2<T>::type* __restrict__ C, const T* __restrict__ Atab,
+    const T* __restrict__ dec) {
+  using V = typename V2<T>::type;
+  constexpr int NP = NK * (NK + 1) / 2;
+  constexpr int PPB = kThreads / NK;  // points per workgroup
+  __shared__ V sb[PPB][NK];
+  __shared__ V sa[PPB][NK];
+  const int lp = threadIdx.x / NK, j = threadIdx.x % NK;
+  const int64_t n0 = (int64_t)blockIdx.x * PPB + lp;
+  const bool act = lp < PPB && n0 <= a.M;
+  int64_t st0 = 0, st1 = 0;
+  T D = T(0);
+  if (act) {
+    int64_t nv[3] = {n0, 0, 0}, nvc[3] = {-n0, 0, 0};
+    st0 = radial_store(a, nv);
+    st1 = radial_store(a, nvc);
+    D = dec[n0];
+    const int g = j / 2;
+    V z = V{T(0), T(0)}, zc = V{T(0), T(0)};
+    if (g < a.npair) {
+      z = C[g * a.pair_stride + st0];
+      zc = C[g * a.pair_stride + st1];
+    }
+    sb[lp][j] = (j & 1) ? V{T(0.5) * (z.y + zc.y) * D, T(-0.5) * (z.x - zc.x) * D}
+                        : V{T(0.5) * (z.x + zc.x) * D, T(0.5) * (z.y - zc.y) * D};
+  }
+  __syncthreads();
+  if (act) {
+    const T* Ar = Atab + n0 * NP;
+    V acc = V{T(0), T(0)};
+#pragma unroll 8
+    for (int k = 0; k < NK; ++k) {
+      const int lo = min(j, k), hi = max(j, k);
+      const T av = Ar[lo * NK - lo * (lo - 1) / 2 + (hi - lo)];
+      acc.x += av * sb[lp][k].x;
+      acc.y += av * sb[lp][k].y;
+    }
+    sa[lp][j] = acc;
+  }
+  __syncthreads();
+  if (act && j < a.npair) {
+    const V pp = V{sa[lp][2 * j].x * D, sa[lp][2 * j].y * D};
+    const V qq = V{sa[lp][2 * j + 1].x * D, sa[lp][2 * j + 1].y * D};
+    C[j * a.pair_stride + st0] = V{pp.x - qq.y, pp.y + qq.x};
+    if (st1 != st0) C[j * a.pair_stride + st1] = V{pp.x + qq.y, -pp.y + qq.x};
+  }
+}
+
 // 1-D four-step: zero the spectrum outside {-M..M} before the inverse transform.
 template <typename T>
 __global__ void zero_band_kernel(typename V2<T>::type* C, int64_t nf, int64_t L1, int64_t L2,
@@ -289,6 +343,14 @@ void launch_radial_nk(Plan* P) {
   int64_t F = 1;
   for (int r = 0; r < P->d; ++r) F *= a.mc;
   a.pair_stride = P->fourstep ? P->nf[0] : F;
+  if (P->d == 1) {
+    constexpr int PPB = kThreads / NK;
+    hipLaunchKernelGGL((mode_radial_1d_kernel<T, NK>), dim3((unsigned)((a.Q + PPB - 1) / PPB)),
+                       dim3(kThreads), 0, P->stream, a, P->gridC.as<typename V2<T>::type>(),
+                       P->atab.as<T>(), P->dec.as<T>());
+    GP_CHECK_LAUNCH();
+    return;
+  }
   hipLaunchKernelGGL((mode_radial_kernel<T, NK>), dim3((unsigned)((a.Q + kThreads - 1) / kThreads)),
                      dim3(kThreads), 0, P->stream, a, P->gridC.as<typename V2<T>::type>(),
                      P->atab.as<T>(), P->d > 1 ? P->rowidx.as<int>() : nullptr, P->dec.as<T>());
