@@ -7,8 +7,10 @@
 // window; everything else is zero), the last stage stores straight to HBM
 // (only the output window later steps read), and the stages in between
 // exchange data through LDS one real component at a time (a padded buffer of
-// L + L/32 reals per sequence).  With radices
-// up to 32 an 8192-point transform is three stages and two exchanges.
+// L + L/32 reals per sequence).  Radices go up to 32 (24 for lengths 3*2^k):
+// an 8192-point transform is three stages with 32 elements per thread
+// (32*32*8) and four with 16 (16*16*16*2); a 6144-point one with 24 elements
+// per thread is four (24*8*8*4).
 // Pruning both windows keeps the empty border of the oversampled grid (points
 // fill a fraction 2*Delta-omega of the period) and the discarded high
 // frequencies out of HBM.
