@@ -278,11 +278,16 @@ typedef struct {
 } gp_server_counters;
 int gp_server_opts_init(gp_server_opts* opts);
 int gp_server_create(const gp_server_opts* opts, gp_server_t* out);
-/* Queue one solve; returns immediately with its id.  Validates the inputs and
- * sizes the request (GP_ENOMEM if it can never fit the budget). */
+/* Queue one solve; returns after sizing the request (which reads its points
+ * and scales), with its id.  Validates the inputs and sizes the request
+ * (GP_ENOMEM if it can never fit the budget).  stream: the hipStream_t on
+ * which pts, sigma, l and y were produced (NULL = the null stream); every
+ * read of them by the server is ordered after the work queued on that stream
+ * at the time of the call (an event recorded there), so the caller need not
+ * synchronise before submitting. */
 int gp_server_submit(gp_server_t srv, int d, int64_t n, const double* pts, const double* sigma,
                      const double* l, double nu, double eta, const double* y, double* alpha,
-                     int64_t* id);
+                     void* stream, int64_t* id);
 /* Block until request id has finished; returns its status. */
 int gp_server_wait(gp_server_t srv, int64_t id, gp_request_info* info);
 int gp_server_poll(gp_server_t srv, int64_t id, int* done);

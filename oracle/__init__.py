@@ -5,9 +5,12 @@ TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
 imports, links or calls anything here, and this package imports nothing from
 the product.
 
-The arithmetic lives in ``oracle.cpp`` (built into ``liboracle.so`` by
-``oracle/build.py``); this module only marshals numpy arrays.  See the header
-of ``oracle.cpp`` for the formulas (Kielstra & Lindsey, arXiv 2407.03608).
+Most of the arithmetic lives in ``oracle.cpp`` (compiled into ``liboracle.so``
+by ``build()`` below, with g++ and OpenMP); see its header for the formulas
+(Kielstra & Lindsey, arXiv 2407.03608).  This module marshals numpy arrays to
+it and adds two plain numpy steps: the Schur complement of eq:postcov
+(``_schur``: one oracle Cholesky, one triangular solve per target column and a
+matrix product) and the assembly of the dense blocks it takes.
 """
 from __future__ import annotations
 
@@ -199,10 +202,16 @@ def chol_solve(L, b) -> np.ndarray:
     return x
 
 
-def gpr_solve_exact(x, sig, l, nu, eta, y) -> np.ndarray:
-    """alpha = (K + eta^2 I)^{-1} y by the oracle Cholesky (eq:gprsolve)."""
+def gpr_solve_exact(x, sig, l, nu, eta, y, lapack: bool = False) -> np.ndarray:
+    """alpha = (K + eta^2 I)^{-1} y (eq:gprsolve) with the exact kernel matrix.
+    The factorisation is the oracle's own Cholesky, or LAPACK's (numpy, a
+    library primitive pinned against the oracle's in the tests) for sizes where
+    the plain loop would take minutes."""
     K = kernel_matrix(x, sig, l, nu)
     K[np.diag_indices_from(K)] += eta * eta
+    if lapack:
+        import scipy.linalg
+        return scipy.linalg.cho_solve(scipy.linalg.cho_factor(K, lower=True), _f64(y))
     return chol_solve(cholesky(K), y)
 
 

@@ -360,13 +360,20 @@ int orc_ktilde_matvec(const orc_plan* p, int64_t n, const double* x, const doubl
 // K~(x, y) formed a second way.  Inserting eq:BWG into eq:Ktilde gives
 //   K~(x,y) = sum_{k',k} w_k'(x) w_k(y) sum_j v~_j sum_{n in G} G^_{k'j}[n] G^_{kj}[n] e^{2 pi i dw n.(x'-y')}
 // and because G^ factorises over dimensions and G is a box, the n-sum is a
-// product of d one-dimensional even (cosine) sums.  Entries K[i*ny + j].
+// product of d one-dimensional even (cosine) sums
+//   S_a = sum_{m=-M..M} exp(-tau m^2) cos(2 pi dw m delta_a)
+//       = 1 + 2 sum_{m=1..M} exp(-tau m^2) cos(2 pi dw m delta_a),
+// tau = 2 pi^2 (s_k'^2 + s_k^2) chi_j^2 dw^2 (s = sigma_k chi_j as in ghat).
+// The Gaussian factors exp(-tau m^2) depend only on (k', k, j) and m, and the
+// cosines only on the pair of points, so both are tabulated once (the pairs
+// k' <= k: the t-sum is symmetric in k', k).  Entries K[i*ny + j].
 int orc_ktilde_entries(const orc_plan* p, int64_t nx, const double* x, const double* sx,
                        const double* lx, int64_t ny, const double* y, const double* sy,
                        const double* ly, double* K) {
   const int d = p->d;
   const int ns = p->n_sigma + 1;
   const int nt = is_se(p) ? 1 : p->n_t + 1;
+  const int64_t M = p->M;
   std::vector<double> xp = mapped(p, nx, x), yp = mapped(p, ny, y);
   std::vector<double> wx(nx * ns), wy(ny * ns);
   orc_weights(p, nx, sx, lx, wx.data());
@@ -374,33 +381,58 @@ int orc_ktilde_entries(const orc_plan* p, int64_t nx, const double* x, const dou
   std::vector<double> t(nt), vt(nt), chi(nt), sk(ns);
   orc_tgrid(p, t.data(), vt.data(), chi.data());
   orc_sigma_nodes(p, sk.data());
+  // pair index q of (k', k), k' <= k, and its (k', k)
+  std::vector<int> qa, qb;
+  for (int kp = 0; kp < ns; ++kp)
+    for (int k = kp; k < ns; ++k) {
+      qa.push_back(kp);
+      qb.push_back(k);
+    }
+  const int64_t nq = (int64_t)qa.size();
+  // per (q, j): the constant (2 pi sa2)^(d/2) (2 pi sb2)^(d/2) v~_j and the
+  // Gaussian factors exp(-tau m^2), m = 1..M
+  std::vector<double> pref((size_t)nq * nt), gau((size_t)nq * nt * M);
+#pragma omp parallel for schedule(static)
+  for (int64_t qj = 0; qj < nq * nt; ++qj) {
+    const int64_t q = qj / nt;
+    const int j = (int)(qj % nt);
+    const double sa2 = sk[qa[q]] * sk[qa[q]] * chi[j] * chi[j];
+    const double sb2 = sk[qb[q]] * sk[qb[q]] * chi[j] * chi[j];
+    pref[qj] = vt[j] * std::pow(2.0 * PI * sa2, 0.5 * d) * std::pow(2.0 * PI * sb2, 0.5 * d);
+    const double tau = 2.0 * PI * PI * (sa2 + sb2) * p->dw * p->dw;
+    for (int64_t m = 1; m <= M; ++m) gau[(size_t)qj * M + (m - 1)] = std::exp(-tau * (double)(m * m));
+  }
 #pragma omp parallel for schedule(dynamic, 1)
-  for (int64_t i = 0; i < nx; ++i)
+  for (int64_t i = 0; i < nx; ++i) {
+    std::vector<double> cs((size_t)d * M);
     for (int64_t jj = 0; jj < ny; ++jj) {
+      for (int a = 0; a < d; ++a) {
+        const double delta = xp[i * d + a] - yp[jj * d + a];
+        for (int64_t m = 1; m <= M; ++m)
+          cs[(size_t)a * M + (m - 1)] = std::cos(2.0 * PI * p->dw * (double)m * delta);
+      }
       double total = 0.0;
-      for (int kp = 0; kp < ns; ++kp)
-        for (int k = 0; k < ns; ++k) {
-          double sum_t = 0.0;
-          for (int j = 0; j < nt; ++j) {
-            double sa2 = sk[kp] * sk[kp] * chi[j] * chi[j];
-            double sb2 = sk[k] * sk[k] * chi[j] * chi[j];
-            double prod = std::pow(2.0 * PI * sa2, 0.5 * d) * std::pow(2.0 * PI * sb2, 0.5 * d);
-            for (int a = 0; a < d; ++a) {
-              double delta = xp[i * d + a] - yp[jj * d + a];
-              double s1 = 0.0;
-              for (int64_t m = -p->M; m <= p->M; ++m) {
-                double m2 = (double)m * (double)m;
-                s1 += std::exp(-2.0 * PI * PI * (sa2 + sb2) * p->dw * p->dw * m2) *
-                      std::cos(2.0 * PI * p->dw * (double)m * delta);
-              }
-              prod *= s1;
-            }
-            sum_t += vt[j] * prod;
+      for (int64_t q = 0; q < nq; ++q) {
+        const int kp = qa[q], k = qb[q];
+        double sum_t = 0.0;
+        for (int j = 0; j < nt; ++j) {
+          const double* g = &gau[((size_t)q * nt + j) * M];
+          double prod = pref[q * nt + j];
+          for (int a = 0; a < d; ++a) {
+            const double* c = &cs[(size_t)a * M];
+            double s1 = 0.0;
+            for (int64_t m = 0; m < M; ++m) s1 += g[m] * c[m];
+            prod *= 1.0 + 2.0 * s1;
           }
-          total += wx[i * ns + kp] * wy[jj * ns + k] * sum_t;
+          sum_t += prod;
         }
+        double wpair = wx[i * ns + kp] * wy[jj * ns + k];
+        if (k != kp) wpair += wx[i * ns + k] * wy[jj * ns + kp];
+        total += wpair * sum_t;
+      }
       K[i * ny + jj] = total;
     }
+  }
   return 0;
 }
 

@@ -63,6 +63,9 @@ PhaseScope::~PhaseScope() {
 }
 
 Plan::~Plan() {
+  // work still queued on the plan's stream may use its buffers
+  if (cg_part.p || gridA.p) (void)hipStreamSynchronize(stream);
+  if (cg_hS) (void)hipHostFree(cg_hS);
   for (auto& ev : events) {
     (void)hipEventDestroy(ev.a);
     (void)hipEventDestroy(ev.b);
@@ -78,17 +81,17 @@ int cg_refined_user(Plan* Pi, Plan* Po, const double* y, double* alpha, double t
                     int* iters_out, double* rel_out, int* passes_out) {
   if (Pi->n != Po->n || Pi->d != Po->d) throw Error{GP_EINVAL, "plans differ in n or d"};
   if (Pi->stream != Po->stream) throw Error{GP_EINVAL, "plans must share a stream"};
+  if (Pi == Po) throw Error{GP_EINVAL, "inner and outer plans must be distinct plans"};
   const int64_t n = Po->n;
   hipStream_t s = Po->stream;
-  DevBuf rb, db, tb;
-  rb.alloc(n * sizeof(double));
-  db.alloc(n * sizeof(double));
-  tb.alloc(n * sizeof(double));
-  double* r = rb.as<double>();  // user order
-  double* dl = db.as<double>();
-  double* tmp = tb.as<double>();
+  // The outer plan only applies its operator (vectors 0, 1) and holds the
+  // sorted right-hand side and residual (6, 7); its vectors 2..4 carry the
+  // caller-order residual, correction and operator output.
   double* Vo = Po->vec.as<double>();
   double* Vi = Pi->vec.as<double>();
+  double* r = Vo + 2 * n;  // user order
+  double* dl = Vo + 3 * n;
+  double* tmp = Vo + 4 * n;
   GP_HIP(hipMemsetAsync(alpha, 0, n * sizeof(double), s));
   gather_sorted(Po, y, Vo + 6 * n);
   const double bb = dot_sorted(Po, Vo + 6 * n, Vo + 6 * n, n);

@@ -18,7 +18,7 @@ namespace gp {
 namespace {
 
 constexpr int kRedThreads = 256;
-constexpr int kRedBlocks = 512;
+constexpr int kRedBlocks = kCgBlocks;
 
 __device__ __forceinline__ double block_sum(double v) {
   __shared__ double red[kRedThreads / 64];
@@ -123,39 +123,37 @@ unsigned nblk(int64_t n) {
   return (unsigned)std::min<int64_t>(std::max<int64_t>(b, 1), kRedBlocks);
 }
 
-struct Scratch {
-  DevBuf part, S;
-  double* hS = nullptr;
-  Scratch() {
-    part.alloc(kRedBlocks * sizeof(double));
-    S.alloc(16 * sizeof(double));
-    GP_HIP(hipHostMalloc((void**)&hS, 16 * sizeof(double), hipHostMallocDefault));
-  }
-  ~Scratch() {
-    if (hS) (void)hipHostFree(hS);
-  }
-};
-
-void dot_into(Plan* P, Scratch& sc, const double* a, const double* b, int slot) {
+void dot_into(Plan* P, const CgScratch& sc, const double* a, const double* b, int slot) {
   const unsigned nb = nblk(P->n);
-  hipLaunchKernelGGL(dot_partial, dim3(nb), dim3(kRedThreads), 0, P->stream, P->n, a, b,
-                     sc.part.as<double>());
-  hipLaunchKernelGGL(dot_final, dim3(1), dim3(kRedThreads), 0, P->stream, (int)nb,
-                     sc.part.as<double>(), sc.S.as<double>(), slot, 0);
+  hipLaunchKernelGGL(dot_partial, dim3(nb), dim3(kRedThreads), 0, P->stream, P->n, a, b, sc.part);
+  hipLaunchKernelGGL(dot_final, dim3(1), dim3(kRedThreads), 0, P->stream, (int)nb, sc.part, sc.S,
+                     slot, 0);
   GP_CHECK_LAUNCH();
 }
 
-double read_slot(Plan* P, Scratch& sc, int slot) {
-  GP_HIP(hipMemcpyAsync(sc.hS + slot, sc.S.as<double>() + slot, sizeof(double),
-                        hipMemcpyDeviceToHost, P->stream));
+// Copy S[0 .. count) to the host and wait for it: into the pinned mirror when
+// the scratch has one, else into `tmp` (pageable; the copy is then staged by
+// the runtime).  Returns the host copy.
+const double* read_S(Plan* P, const CgScratch& sc, int count, double* tmp) {
+  double* dst = sc.hS ? sc.hS : tmp;
+  GP_HIP(hipMemcpyAsync(dst, sc.S, count * sizeof(double), hipMemcpyDeviceToHost, P->stream));
   GP_HIP(hipStreamSynchronize(P->stream));
-  return sc.hS[slot];
+  return dst;
+}
+
+double read_slot(Plan* P, const CgScratch& sc, int slot) {
+  double tmp[kCgScalars];
+  return read_S(P, sc, slot + 1, tmp)[slot];
 }
 
 }  // namespace
 
+CgScratch plan_cg_scratch(Plan* P) {
+  return CgScratch{P->cg_part.as<double>(), P->cg_S.as<double>(), P->cg_hS};
+}
+
 double dot_sorted(Plan* P, const double* a, const double* b, int64_t) {
-  Scratch sc;
+  const CgScratch sc = plan_cg_scratch(P);
   dot_into(P, sc, a, b, 5);
   return read_slot(P, sc, 5);
 }
@@ -165,7 +163,7 @@ void residual_norms(Plan* P, const double* b, const double* x, double* rr, doubl
   matvec_sorted(P, x, t, 1);
   hipLaunchKernelGGL(residual, dim3(nblk(P->n)), dim3(kRedThreads), 0, P->stream, P->n, b, t, t);
   GP_CHECK_LAUNCH();
-  Scratch sc;
+  const CgScratch sc = plan_cg_scratch(P);
   dot_into(P, sc, t, t, 5);
   *rr = read_slot(P, sc, 5);
   dot_into(P, sc, b, b, 5);
@@ -176,12 +174,18 @@ void residual_norms(Plan* P, const double* b, const double* x, double* rr, doubl
 // Returns GP_OK or GP_ENOCONV.
 int cg_solve_sorted(Plan* P, const double* b, double* x, bool x_zero, double tol, int max_iter,
                     int replace_every, int* iters, double* rel_res) {
+  return cg_solve_sorted_with(P, plan_cg_scratch(P), b, x, x_zero, tol, max_iter, replace_every,
+                              iters, rel_res);
+}
+
+int cg_solve_sorted_with(Plan* P, const CgScratch& sc, const double* b, double* x, bool x_zero,
+                         double tol, int max_iter, int replace_every, int* iters,
+                         double* rel_res) {
   const int64_t n = P->n;
   double* V = P->vec.as<double>();
   double* r = V + 3 * n;
   double* p = V + 4 * n;
   double* Ap = V + 5 * n;
-  Scratch sc;
   hipStream_t s = P->stream;
   const unsigned nb = nblk(n);
 
@@ -195,8 +199,10 @@ int cg_solve_sorted(Plan* P, const double* b, double* x, bool x_zero, double tol
   GP_CHECK_LAUNCH();
   dot_into(P, sc, b, b, 3);
   dot_into(P, sc, r, r, 0);
-  const double bb = read_slot(P, sc, 3);
-  double rr = read_slot(P, sc, 0);
+  double tmp[kCgScalars];
+  const double* hs = read_S(P, sc, 4, tmp);
+  const double bb = hs[3];
+  double rr = hs[0];
   if (bb == 0.0) {
     *iters = 0;
     *rel_res = 0;
@@ -211,7 +217,7 @@ int cg_solve_sorted(Plan* P, const double* b, double* x, bool x_zero, double tol
     *rel_res = std::sqrt(rr / bb);
     return GP_OK;
   }
-  hipLaunchKernelGGL(cg_init_flags, dim3(1), dim3(64), 0, s, sc.S.as<double>(), stop2);
+  hipLaunchKernelGGL(cg_init_flags, dim3(1), dim3(64), 0, s, sc.S, stop2);
   GP_CHECK_LAUNCH();
   // Batches grow with the iteration count (at most 1/16 of the iterations
   // done so far are queued beyond convergence) and stay short when an
@@ -230,32 +236,31 @@ int cg_solve_sorted(Plan* P, const double* b, double* x, bool x_zero, double tol
       {
         PhaseScope ps(P, PH_CG);
         dot_into(P, sc, p, Ap, 1);
-        hipLaunchKernelGGL(update_xr, dim3(nb), dim3(kRedThreads), 0, s, n, sc.S.as<double>(), x,
-                           r, p, Ap, sc.part.as<double>());
+        hipLaunchKernelGGL(update_xr, dim3(nb), dim3(kRedThreads), 0, s, n, sc.S, x,
+                           r, p, Ap, sc.part);
         GP_CHECK_LAUNCH();
       }
       if (replace_every > 0 && queued % replace_every == 0) {
         matvec_sorted(P, x, Ap, 1);
         hipLaunchKernelGGL(residual, dim3(nb), dim3(kRedThreads), 0, s, n, b, Ap, r);
         hipLaunchKernelGGL(dot_partial, dim3(nb), dim3(kRedThreads), 0, s, n, r, r,
-                           sc.part.as<double>());
+                           sc.part);
         GP_CHECK_LAUNCH();
       }
       {
         PhaseScope ps(P, PH_CG);
         hipLaunchKernelGGL(dot_final, dim3(1), dim3(kRedThreads), 0, s, (int)nb,
-                           sc.part.as<double>(), sc.S.as<double>(), 0, 1);
-        hipLaunchKernelGGL(update_p, dim3(nb), dim3(kRedThreads), 0, s, n, sc.S.as<double>(), r, p);
+                           sc.part, sc.S, 0, 1);
+        hipLaunchKernelGGL(update_p, dim3(nb), dim3(kRedThreads), 0, s, n, sc.S, r, p);
         GP_CHECK_LAUNCH();
       }
     }
-    GP_HIP(hipMemcpyAsync(sc.hS, sc.S.as<double>(), 9 * sizeof(double), hipMemcpyDeviceToHost, s));
-    GP_HIP(hipStreamSynchronize(s));
+    hs = read_S(P, sc, 9, tmp);
     ms_per_iter = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
                       .count() / batch;
-    rr = sc.hS[0];
-    done = sc.hS[7] != 0.0;
-    done_iters = (int)sc.hS[8];
+    rr = hs[0];
+    done = hs[7] != 0.0;
+    done_iters = (int)hs[8];
     if (!std::isfinite(rr)) throw Error{GP_EDEVICE, "CG breakdown: non-finite residual"};
     if (progress > 0 && done_iters / progress > last_print) {
       last_print = done_iters / progress;

@@ -153,6 +153,11 @@ struct Plan {
   DevBuf tw4;                 // four-step twiddles (1-D, T complex, length nf)
   DevBuf gridA, gridB, gridB2, gridC;
   DevBuf vec;                 // fp64 scratch vectors for matvec / CG (sorted order)
+  // CG reductions (allocated once per plan): per-block partial sums, the
+  // scalar slots of the solver and a pinned host mirror of those slots
+  DevBuf cg_part;             // double [kCgBlocks]
+  DevBuf cg_S;                // double [kCgScalars]
+  double* cg_hS = nullptr;    // pinned host, kCgScalars
   size_t device_bytes = 0;
   // optional per-phase event timing
   bool timing = false;
@@ -211,6 +216,20 @@ void gather_sorted(Plan* P, const double* x_user, double* x_sorted);
 void scatter_user(Plan* P, const double* x_sorted, double* x_user);
 
 // cg.hip
+// Device memory a CG solve reduces into: `part` holds one partial sum per
+// reduction block (kCgBlocks), `S` the solver's scalar slots (kCgScalars);
+// hS is a pinned host mirror of S, or null (reads then go through a
+// synchronous copy to the stack).
+constexpr int kCgBlocks = 512;
+constexpr int kCgScalars = 16;
+struct CgScratch {
+  double* part;
+  double* S;
+  double* hS;
+};
+CgScratch plan_cg_scratch(Plan* P);
+int cg_solve_sorted_with(Plan* P, const CgScratch& sc, const double* b, double* x, bool x_zero,
+                         double tol, int max_iter, int replace_every, int* iters, double* rel_res);
 int cg_solve_sorted(Plan* P, const double* b, double* x, bool x_zero, double tol, int max_iter,
                     int replace_every, int* iters, double* rel_res);
 double dot_sorted(Plan* P, const double* a, const double* b, int64_t n);

@@ -13,11 +13,14 @@
 // the imaginary part of complex grid g, so every FFT is complex-to-complex and
 // the mode kernel separates the two spectra with b(n) = (Z(n) + conj Z(-n))/2.
 //
-// Spreading is a gather: each workgroup owns one tile of the active fine grid,
-// collects every point whose window reaches it (the points are bin-sorted by
-// the tile of their first window cell, so the sources are the 2^d (or more)
-// neighbouring bins), accumulates in LDS with LDS atomics and writes its tile
-// with plain coalesced stores.  No global atomics and no zero-fill pass.
+// Spreading is a gather: each workgroup owns one tile (or sub-tile) of the
+// active fine grid, collects every point whose window reaches it (the points
+// are bin-sorted by the tile of their first window cell, so the sources are
+// the 2^d (or more) neighbouring bins), and each thread sums the contributions
+// to the cells it owns in registers (owner-computes: no atomics, a fixed
+// summation order) before writing them with plain coalesced stores.  No global
+// atomics and no zero-fill pass.  An LDS-atomic variant (per-(point, row)
+// items) is kept as an option.
 #include <algorithm>
 #include <climits>
 #include <cmath>

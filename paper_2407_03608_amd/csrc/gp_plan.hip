@@ -1013,7 +1013,7 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
     bytes += (size_t)P->a_rows * (P->nkp * (P->nkp + 1) / 2) * ts + rowmap.size() * sizeof(int);
   else
     bytes += (size_t)P->nt_eff * P->nk * (P->M + 1) * ts * 2;
-  bytes += (size_t)n * 8 * sizeof(double);  // vectors
+  bytes += (size_t)n * 8 * sizeof(double) + (kCgBlocks + kCgScalars) * sizeof(double);  // vectors
   bytes += (size_t)nf * cs * 2;
   P->device_bytes = bytes;
   if (bytes_out) *bytes_out = bytes;
@@ -1165,6 +1165,9 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
   P->gridC.alloc((size_t)G * szC * cs);
   if (P->fourstep) GP_HIP(hipMemsetAsync(P->gridA.p, 0, P->gridA.bytes, s));
   P->vec.alloc((size_t)n * 8 * sizeof(double));
+  P->cg_part.alloc(kCgBlocks * sizeof(double));
+  P->cg_S.alloc(kCgScalars * sizeof(double));
+  GP_HIP(hipHostMalloc((void**)&P->cg_hS, kCgScalars * sizeof(double), hipHostMallocDefault));
   GP_HIP(hipStreamSynchronize(s));
   return GP_OK;
 }

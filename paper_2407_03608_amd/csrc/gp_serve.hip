@@ -33,6 +33,14 @@ struct SRequest {
   double rel_res = 0;
   bool done = false;
   std::string err;
+  // recorded on the caller's stream at submit: the inputs are ready once it
+  // has completed
+  hipEvent_t ready = nullptr;
+  void release_event() {
+    if (ready) (void)hipEventDestroy(ready);
+    ready = nullptr;
+  }
+  ~SRequest() { release_event(); }
 };
 
 struct Server {
@@ -80,6 +88,7 @@ size_t request_bytes(Server& S, SRequest& r) {
 }
 
 void run_request(Server& S, SRequest& r, hipStream_t st) {
+  GP_HIP(hipStreamWaitEvent(st, r.ready, 0));
   gp_opts o;
   fill_opts(S, 0, st, &o);
   Plan P64;
@@ -163,6 +172,7 @@ void worker(Server* S, int slot) {
       r->status = GP_EDEVICE;
       r->err = e.what();
     }
+    r->release_event();
     {
       std::lock_guard<std::mutex> lk(S->mu);
       S->bytes_in_use -= r->bytes;
@@ -259,7 +269,7 @@ int gp_server_create(const gp_server_opts* opts, gp_server_t* out) {
 
 int gp_server_submit(gp_server_t h, int d, int64_t n, const double* pts, const double* sigma,
                      const double* l, double nu, double eta, const double* y, double* alpha,
-                     int64_t* id) {
+                     void* stream, int64_t* id) {
   return sguard([&] {
     if (!h || !pts || !sigma || !l || !y || !alpha || !id) throw Error{GP_EINVAL, "null argument"};
     Server& S = h->S;
@@ -274,6 +284,11 @@ int gp_server_submit(gp_server_t h, int d, int64_t n, const double* pts, const d
     r->nu = nu;
     r->eta = eta;
     r->t_submit = S.now();
+    // the inputs may still be in production on the caller's stream: every
+    // read of them (the size query here, the solve later) waits for this event
+    GP_HIP(hipEventCreateWithFlags(&r->ready, hipEventDisableTiming));
+    GP_HIP(hipEventRecord(r->ready, static_cast<hipStream_t>(stream)));
+    GP_HIP(hipStreamWaitEvent(S.qstream, r->ready, 0));
     r->bytes = request_bytes(S, *r);  // validates the inputs too
     if (r->bytes > S.o.max_device_bytes)
       throw Error{GP_ENOMEM, "request needs " + std::to_string(r->bytes) +

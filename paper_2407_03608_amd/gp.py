@@ -246,7 +246,7 @@ def load(path: str = LIB_PATH):
     L.gp_server_create.argtypes = [ctypes.POINTER(GpServerOpts), ctypes.POINTER(_c_p)]
     L.gp_server_create.restype = _c_i
     L.gp_server_submit.argtypes = [_c_p, _c_i, _c_i64, _c_p, _c_p, _c_p, _c_d, _c_d, _c_p, _c_p,
-                                   ctypes.POINTER(_c_i64)]
+                                   _c_p, ctypes.POINTER(_c_i64)]
     L.gp_server_submit.restype = _c_i
     L.gp_server_wait.argtypes = [_c_p, _c_i64, ctypes.POINTER(GpRequestInfo)]
     L.gp_server_wait.restype = _c_i
@@ -482,16 +482,20 @@ class Server:
         self._h = h
         self._live = {}
 
-    def submit(self, x, sigma, l, nu, eta, y) -> int:
+    def submit(self, x, sigma, l, nu, eta, y, stream=None) -> int:
+        """Queue a solve.  `stream` is the torch stream the inputs were made on
+        (default: the current stream); the server orders its reads after it."""
         x = _dev(x, "x")
         if x.dim() == 1:
             x = x[:, None].contiguous()
         sigma, l, y = _dev(sigma, "sigma"), _dev(l, "l"), _dev(y, "y")
         alpha = torch.empty_like(y)
+        s = stream if stream is not None else torch.cuda.current_stream()
         rid = _c_i64()
         _check(load().gp_server_submit(self._h, x.shape[1], x.shape[0], x.data_ptr(),
                                        sigma.data_ptr(), l.data_ptr(), float(nu), float(eta),
-                                       y.data_ptr(), alpha.data_ptr(), ctypes.byref(rid)))
+                                       y.data_ptr(), alpha.data_ptr(),
+                                       ctypes.c_void_p(s.cuda_stream), ctypes.byref(rid)))
         self._live[rid.value] = (x, sigma, l, y, alpha)
         return rid.value
 

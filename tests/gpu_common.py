@@ -22,6 +22,13 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def max_rel(a, b):
+    """Largest element-wise error, relative to the largest reference element."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
 def oracle_params(info) -> O.Params:
     """The K~ the plan realises, handed to the oracle (parameters only)."""
     return O.Params(d=info["d"], nu=info["nu"], t_min=info["t_min"], t_max=info["t_max"],

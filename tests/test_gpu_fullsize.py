@@ -11,7 +11,7 @@ import pytest
 
 import oracle as O
 from paper_2407_03608_amd import inputs
-from tests.gpu_common import cuda, host, oracle_params, rel, say
+from tests.gpu_common import cuda, host, max_rel, oracle_params, rel, say
 
 pytestmark = pytest.mark.gpu
 
@@ -26,26 +26,65 @@ def gp():
     return g
 
 
-def _sparse_check(gp, P, prob, n_nz=3, n_near=6, n_far=3, seed=0, bar=1e-6):
+def _cells(info, x):
+    """First window cell of each point along each dimension, in the active box
+    (the plan's map x' = (x - c) s, fine-grid position g = n_f/2 + n_f dw x')."""
+    d = info["d"]
+    out = np.empty((x.shape[0], d), dtype=np.int64)
+    for a in range(d):
+        nf = info["nf"][a]
+        g = 0.5 * nf + nf * info["dw"] * (x[:, a] - info["center"][a]) * info["scale"]
+        out[:, a] = np.ceil(g - 0.5 * info["w"]).astype(np.int64) - info["lo"][a]
+    return out
+
+
+def _edge_sets(info, x, rng, k):
+    """Points at the box faces (extreme coordinates), points whose window
+    starts on the last cell of a spreading tile in every dimension (it reaches
+    2^d tiles), and points at the corner of a 2x2 interpolation block."""
+    d = info["d"]
+    box = []
+    for a in range(d):
+        box += [int(np.argmin(x[:, a])), int(np.argmax(x[:, a]))]
+    c = _cells(info, x)
+    t = np.array(info["tile"][:d])
+    tile_corner = np.flatnonzero(np.all(c % t == t - 1, axis=1))
+    blk = np.all(c[:, :2] % (2 * t[:2]) == 2 * t[:2] - 1, axis=1)
+    block_corner = np.flatnonzero(blk)
+    pick = lambda v: list(rng.choice(v, size=min(k, v.size), replace=False)) if v.size else []
+    return box, pick(tile_corner), pick(block_corner)
+
+
+def _sparse_check(gp, P, prob, n_nz=16, n_near=8, n_far=32, seed=0, bar=1e-6):
+    """K~ alpha for a sparse alpha (n_nz non-zeros, some at box faces and tile
+    corners) at >= 200 sampled outputs: the non-zeros, their nearest
+    neighbours, box-face, tile-corner and block-corner points and random ones,
+    each against the oracle's sum of K~ entries."""
+    info = P.info()
     rng = np.random.default_rng(seed)
-    nz = rng.choice(prob.n, size=n_nz, replace=False)
+    box, tcorner, bcorner = _edge_sets(info, prob.x, rng, 24)
+    nz = list(dict.fromkeys(box[:2] + tcorner[:3] + bcorner[:3]))
+    rest = rng.choice(prob.n, size=n_nz, replace=False)
+    nz = np.array(list(dict.fromkeys(nz + list(rest)))[:n_nz])
     a = np.zeros(prob.n)
-    a[nz] = rng.standard_normal(n_nz)
+    a[nz] = rng.standard_normal(nz.size)
     got = host(P.matvec(cuda(a)))
-    # outputs: the non-zeros, their nearest neighbours, a few random points
-    samp = list(nz)
+    samp = list(nz) + box + tcorner + bcorner
     for j in nz:
         d2 = ((prob.x - prob.x[j]) ** 2).sum(1)
         d2[j] = np.inf
         samp += list(np.argpartition(d2, n_near)[:n_near])
     samp += list(rng.choice(prob.n, size=n_far, replace=False))
-    samp = np.array(samp)
-    K = O.ktilde_entries(oracle_params(P.info()), prob.x[samp], prob.sigma[samp], prob.l[samp],
+    samp = np.array(list(dict.fromkeys(int(v) for v in samp)))
+    assert samp.size >= 200 and nz.size == n_nz
+    K = O.ktilde_entries(oracle_params(info), prob.x[samp], prob.sigma[samp], prob.l[samp],
                          prob.x[nz], prob.sigma[nz], prob.l[nz])
     ref = K @ a[nz]
-    e = rel(got[samp], ref)
-    say(f"  sampled outputs ({len(samp)}) vs oracle K~ entries: {e:.3e}")
-    assert e <= bar
+    e, em = rel(got[samp], ref), max_rel(got[samp], ref)
+    say(f"  {samp.size} sampled outputs of {nz.size} non-zeros ({len(tcorner)} tile-corner, "
+        f"{len(bcorner)} block-corner, {len(box)} box-face points) vs oracle K~ entries: "
+        f"{e:.3e} (2-norm), {em:.3e} (max element / max |ref|)")
+    assert e <= bar and em <= bar
     return e
 
 

@@ -11,7 +11,7 @@ import pytest
 
 import oracle as O
 from paper_2407_03608_amd import inputs
-from tests.gpu_common import cuda, host, oracle_params, rel, say
+from tests.gpu_common import cuda, host, max_rel, oracle_params, rel, say
 
 pytestmark = pytest.mark.gpu
 
@@ -43,8 +43,10 @@ def _check_matvec(gp, prob, tol=1e-8, precision=0, bar=FP64_TOL, seed=0, **opts)
     got = host(P.matvec(cuda(a)))
     ref = O.ktilde_matvec(oracle_params(info), prob.x, prob.sigma, prob.l, a)
     e = rel(got, ref)
-    say(f"  rel err vs oracle K~ = {e:.3e}")
+    em = max_rel(got, ref)
+    say(f"  rel err vs oracle K~ = {e:.3e} (2-norm), {em:.3e} (max element / max |ref|)")
     assert e <= bar, e
+    assert em <= bar, em
     return P, info, a, got, ref
 
 
@@ -231,6 +233,35 @@ def test_cg_matches_cholesky_of_ktilde(gp):
     say("  cg", ci)
     assert ci["status"] == 0
     assert rel(host(a), ref) <= 1e-6
+
+
+@pytest.mark.parametrize("d,M,replace_every", [(2, 22, 0), (1, 120, 20)])
+def test_cg_solve_refined_vs_cholesky(gp, d, M, replace_every):
+    """Mixed precision (gp_cg_solve_refined): fp32-bulk inner CG inside fp64
+    iterative refinement.  The refinement targets the fp64 operator, so its
+    solution must match the oracle's Cholesky solution of K~ + eta^2 I
+    (eq:gprsolve, the fp64 plan's K~) within 1e-6; the inner plan shares
+    Delta-omega and M and chooses its own N_sigma, N_t and window for 1e-4."""
+    prob = inputs.random_small(d, 300, seed=23 + d, nu=1.5, lmin=0.1, lmax=0.2, eta=0.3)
+    P64 = _plan(gp, prob, tol=1e-10, M=M)
+    info = P64.info()
+    P32 = _plan(gp, prob, tol=1e-4, precision=1, M=M, dw=info["dw"])
+    i32 = P32.info()
+    say(f"  fp64 plan N_sigma={info['n_sigma']} N_t={info['n_t']} w={info['w']}; "
+        f"fp32 plan N_sigma={i32['n_sigma']} N_t={i32['n_t']} w={i32['w']}")
+    Kt = O.ktilde_entries(oracle_params(info), prob.x, prob.sigma, prob.l)
+    ref = O.chol_solve(O.cholesky(Kt + prob.eta ** 2 * np.eye(prob.n)), prob.y)
+    a, ci = gp.cg_solve_refined(P32, P64, cuda(prob.y), tol=1e-11, inner_tol=3e-3,
+                                max_iter=20000, max_refine=30, replace_every=replace_every)
+    e = rel(host(a), ref)
+    say(f"  refined: {ci['iters']} inner iterations in {ci['refinements']} passes, "
+        f"outer rel res {ci['rel_res_true']:.2e}, solution vs Cholesky {e:.3e}")
+    assert ci["status"] == 0 and ci["refinements"] >= 2
+    assert e <= 1e-6
+    # the residual it reports is the fp64 operator's
+    assert abs(P64.residual(cuda(prob.y), a) - ci["rel_res_true"]) <= 1e-3 * ci["rel_res_true"] + 1e-15
+    with pytest.raises(gp.GpError):
+        gp.cg_solve_refined(P64, P64, cuda(prob.y))
 
 
 def test_cg_replacement_and_x0(gp):

@@ -44,30 +44,82 @@ def _requests(k):
     return out
 
 
-def test_server_alone_vs_mix(gp):
+@pytest.mark.parametrize("routing", ["split", "all_fp32"])
+def test_server_alone_vs_mix(gp, routing):
+    """Each request gives the same bits alone (one slot) and in a mix of
+    concurrent requests (six slots, smallest-first admission).  "split" puts
+    the fp64-routing threshold at the median fp64 plan size, so both paths
+    (plain fp64 CG and fp32-bulk CG inside fp64 refinement) run in the mix;
+    "all_fp32" routes every request to the refined fp32-bulk path."""
     probs = _requests(16)
     dev = [(cuda(p.x), cuda(p.sigma), cuda(p.l), cuda(p.y)) for p in probs]
+    if routing == "split":
+        b64 = sorted(gp.plan_query(x, s, l, p.nu, p.eta, 1e-8) for p, (x, s, l, _) in zip(probs, dev))
+        thr = (b64[len(b64) // 2 - 1] + b64[len(b64) // 2]) // 2 + 1
+    else:
+        thr = 0
     # alone: one slot, one request at a time
-    S1 = gp.Server(max_slots=1, max_iter=6000)
+    S1 = gp.Server(max_slots=1, max_iter=6000, fp64_below_bytes=thr)
     alone = []
     for p, (x, s, l, y) in zip(probs, dev):
         rid = S1.submit(x, s, l, p.nu, p.eta, y)
         a, info = S1.wait(rid)
-        say(f"  alone req d={p.d} n={p.n} nu={p.nu} iters={info['iters']} rel={info['rel_res']:.2e} status={info['status']}")
+        say(f"  alone req d={p.d} n={p.n} nu={p.nu} path={'fp64' if info['precision'] == 0 else 'fp32-bulk'} "
+            f"iters={info['iters']} rel={info['rel_res']:.2e} status={info['status']}")
         alone.append((host(a), info))
     S1.close()
     # mix: everything submitted at once to a 6-slot server (smallest-first admission)
-    S6 = gp.Server(max_slots=6, max_iter=6000, policy=gp.GP_SERVE_SMALLEST)
+    S6 = gp.Server(max_slots=6, max_iter=6000, policy=gp.GP_SERVE_SMALLEST, fp64_below_bytes=thr)
     ids = [S6.submit(x, s, l, p.nu, p.eta, y) for p, (x, s, l, y) in zip(probs, dev)]
     mix = [S6.wait(i) for i in ids]
     st = S6.stats()
     say(f"  server stats {st}")
     S6.close()
     assert st["peak_running"] > 1
+    paths = [im["precision"] for _, im in mix]
+    say(f"  paths in the mix: {paths.count(gp.GP_FP64)} fp64, {paths.count(gp.GP_FP32_BULK)} fp32-bulk")
+    if routing == "split":
+        assert gp.GP_FP64 in paths and gp.GP_FP32_BULK in paths
+    else:
+        assert all(q == gp.GP_FP32_BULK for q in paths)
     for (aa, ia), (am, im) in zip(alone, mix):
-        assert ia["status"] == im["status"]
-        assert ia["iters"] == im["iters"]
+        assert ia["precision"] == im["precision"]
+        assert ia["status"] == im["status"] == 0
+        assert ia["iters"] == im["iters"] and ia["refinements"] == im["refinements"]
+        assert im["rel_res"] <= 1e-6
         assert np.array_equal(aa, host(am))
+
+
+def test_server_orders_reads_after_the_producer_stream(gp):
+    """Inputs still being written on a side stream at submit time: the server
+    waits for that stream's work (an event recorded at submit) before reading
+    them, so the result equals that of inputs produced synchronously."""
+    import torch
+    p = _requests(2)[1]
+    S = gp.Server(max_slots=2, max_iter=6000)
+    x, s, l, y = cuda(p.x), cuda(p.sigma), cuda(p.l), cuda(p.y)
+    torch.cuda.synchronize()
+    ref, iref = S.wait(S.submit(x, s, l, p.nu, p.eta, y))
+    ref = host(ref)
+    hx, hs, hl, hy = (torch.from_numpy(np.ascontiguousarray(v)).pin_memory()
+                      for v in (p.x, p.sigma, p.l, p.y))
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        big = torch.randn(4096, 4096, device="cuda", dtype=torch.float32)
+        for _ in range(24):   # tens of milliseconds of work queued before the inputs
+            big = big @ big
+            big = big / big.norm()
+        zero = 0.0 * big[0, 0].double()
+        xs = hx.to("cuda", non_blocking=True) + zero
+        ss = hs.to("cuda", non_blocking=True) + zero
+        ls = hl.to("cuda", non_blocking=True) + zero
+        ys = hy.to("cuda", non_blocking=True) + zero
+        rid = S.submit(xs, ss, ls, p.nu, p.eta, ys)   # stream defaults to the current (side)
+    got, info = S.wait(rid)
+    S.close()
+    say(f"  producer-stream request: iters {info['iters']} vs {iref['iters']}")
+    assert info["status"] == 0 and info["iters"] == iref["iters"]
+    assert np.array_equal(host(got), ref)
 
 
 def test_server_precision_routing(gp):

@@ -101,6 +101,9 @@ def test_cholesky_solve_matches_lapack():
     ref = np.linalg.solve(K, p.y)
     assert np.linalg.norm(a - ref) / np.linalg.norm(ref) < 1e-10
     assert np.linalg.norm(K @ a - p.y) / np.linalg.norm(p.y) < 1e-12
+    # the LAPACK-factorised variant used for large reference solves agrees
+    al = O.gpr_solve_exact(p.x, p.sigma, p.l, p.nu, p.eta, p.y, lapack=True)
+    assert np.linalg.norm(al - a) / np.linalg.norm(a) < 1e-10
 
 
 def test_exact_matvec_rows_match_dense():
@@ -145,6 +148,45 @@ def test_chebyshev_nodes_and_partition_of_unity():
     for j in range(13):
         P = O.lagrange(sk, sk[j])
         assert np.abs(P - np.eye(13)[j]).max() < 1e-12
+
+
+@pytest.mark.parametrize("nsig", [1, 2, 3, 5, 8, 13, 20, 31])
+def test_chebyshev_lobatto_node_positions(nsig):
+    """eq:chebscheme: the width nodes are the Chebyshev-Lobatto points, i.e. the
+    N_sigma + 1 extrema of T_{N_sigma} on [-1, 1] mapped affinely onto
+    [sigma_min, sigma_max].  The extrema are found independently of the oracle:
+    the endpoints plus the roots of T'_{N_sigma} from numpy's Chebyshev class."""
+    from numpy.polynomial import chebyshev as C
+    smin, smax = 0.037, 0.21
+    p = _params(1, 1.5, np.array([smin, smax]), nsig, 0.1, 10)
+    sk = np.sort(O.sigma_nodes(p))
+    inner = np.sort(C.Chebyshev.basis(nsig).deriv().roots().real) if nsig > 1 else np.array([])
+    ext = np.concatenate([[-1.0], inner, [1.0]])
+    want = smin + 0.5 * (ext + 1.0) * (smax - smin)
+    assert sk.shape == want.shape
+    assert np.abs(sk - want).max() < 1e-13 * smax
+    # each is an extremum: |T_n| = 1 there
+    tn = C.Chebyshev.basis(nsig)(2 * (sk - smin) / (smax - smin) - 1)
+    assert np.allclose(np.abs(tn), 1.0, atol=1e-11)
+
+
+@pytest.mark.parametrize("nsig", [4, 6, 8, 12, 16, 24, 32])
+def test_chebyshev_lobatto_lebesgue_constant(nsig):
+    """The interpolation of eq:chebscheme on the oracle's nodes has Lebesgue
+    constant max_s sum_k |P_k(s)| <= (2/pi) ln(N_sigma + 1) + 1, the bound for
+    Chebyshev extrema; equispaced nodes exceed it from N_sigma = 8 on, so the
+    check sees a node set of the wrong family."""
+    smin, smax = 0.1, 0.45
+    p = _params(1, 1.5, np.array([smin, smax]), nsig, 0.1, 10)
+    sk = O.sigma_nodes(p)
+    grid = np.linspace(smin, smax, 4001)
+    lam = max(np.abs(O.lagrange(sk, s)).sum() for s in grid)
+    bound = 2 / np.pi * np.log(nsig + 1) + 1
+    assert 1.0 <= lam <= bound, (lam, bound)
+    if nsig >= 8:
+        eq = np.linspace(smax, smin, nsig + 1)
+        lam_eq = max(np.abs(O.lagrange(eq, s)).sum() for s in grid)
+        assert lam_eq > bound
 
 
 @pytest.mark.parametrize("kappa,nsig", [(1.5, 6), (2.0, 10), (3.0, 14), (4.0, 20)])
