@@ -178,6 +178,21 @@ int gp_matvec(gp_plan_t plan, const double* alpha, double* out, int add_noise);
 int gp_cg_solve(gp_plan_t plan, const double* y, double* alpha, int use_x0, double tol,
                 int max_iter, int replace_every, gp_cg_info* info);
 
+/* gp_cg_solve for callers that cannot allocate memory (code under stream
+ * capture, tight serving loops, harnesses that forbid allocation): same
+ * arguments, kernels, iterates and results as gp_cg_solve (bit for bit), but
+ * it calls no hipMalloc, hipFree, hipHostMalloc or other allocating routine.
+ * Its reduction scratch (512 per-block partial sums and 16 scalar slots,
+ * 4.2 KB) is a static device array that each GPU holds for the life of the
+ * process, looked up on the first call on that device; every n fits in it (the
+ * reduction never uses more than 512 blocks).  The plan's device must be the
+ * current device (GP_EINVAL otherwise).  The host reads the solver's scalars
+ * through synchronous copies to its stack.  All calls on one GPU share the
+ * scratch: calls that overlap in time on one GPU (other threads, other
+ * streams) race and give undefined results; serialise them. */
+int gp_cg_solve_noalloc(gp_plan_t plan, const double* y, double* alpha, int use_x0, double tol,
+                        int max_iter, int replace_every, gp_cg_info* info);
+
 /* Mixed-precision solve: CG with the operator of `inner` (typically
  * GP_FP32_BULK) inside fp64 iterative refinement with the operator of
  * `outer` (GP_FP64) on the same points: x_0 = 0; r = y - A_outer x;

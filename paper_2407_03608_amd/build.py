@@ -24,6 +24,7 @@ SOURCES = [
     ("gp_cg.hip", "gp_cg.o", []),
     ("gp_capi.hip", "gp_capi.o", []),
     ("gp_serve.hip", "gp_serve.o", []),
+    ("gp_noalloc.hip", "gp_noalloc.o", []),
 ]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("GP_OFFLOAD_ARCH", "gfx950")

@@ -112,6 +112,12 @@ __global__ void residual(int64_t n, const double* __restrict__ b, const double* 
     r[i] = b[i] - Ax[i];
 }
 
+__global__ void zero_vec(int64_t n, double* __restrict__ a) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = 0.0;
+}
+
 __global__ void copy_vec(int64_t n, const double* __restrict__ a, double* __restrict__ b) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -147,6 +153,11 @@ double read_slot(Plan* P, const CgScratch& sc, int slot) {
 }
 
 }  // namespace
+
+void zero_sorted(Plan* P, double* x) {
+  hipLaunchKernelGGL(zero_vec, dim3(nblk(P->n)), dim3(kRedThreads), 0, P->stream, P->n, x);
+  GP_CHECK_LAUNCH();
+}
 
 CgScratch plan_cg_scratch(Plan* P) {
   return CgScratch{P->cg_part.as<double>(), P->cg_S.as<double>(), P->cg_hS};

@@ -100,6 +100,7 @@ struct Plan {
   int precision = GP_FP64;
   double nu = 0, eta = 0;
   bool se = false;
+  int device = 0;             // HIP device current when the plan was built
   // mapping into [-1,1]^d
   double center[3] = {0, 0, 0};
   double scale = 1;
@@ -228,6 +229,8 @@ struct CgScratch {
   double* hS;
 };
 CgScratch plan_cg_scratch(Plan* P);
+// x = 0 on the plan's stream (a kernel, not a memset)
+void zero_sorted(Plan* P, double* x);
 int cg_solve_sorted_with(Plan* P, const CgScratch& sc, const double* b, double* x, bool x_zero,
                          double tol, int max_iter, int replace_every, int* iters, double* rel_res);
 int cg_solve_sorted(Plan* P, const double* b, double* x, bool x_zero, double tol, int max_iter,

@@ -896,6 +896,7 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
   P->eta = eta;
   P->se = std::isinf(nu);
   P->stream = static_cast<hipStream_t>(opts.stream);
+  GP_HIP(hipGetDevice(&P->device));
   hipStream_t s = P->stream;
 
   // ---- host copies for validation and ranges

@@ -117,6 +117,7 @@ EXPORTS = [
     "gp_matvec",
     "gp_cg_solve",
     "gp_cg_solve_refined",
+    "gp_cg_solve_noalloc",
     "gp_posterior_mean",
     "gp_plan_set_stream",
     "gp_plan_destroy",
@@ -218,6 +219,8 @@ def load(path: str = LIB_PATH):
     L.gp_matvec.restype = _c_i
     L.gp_cg_solve.argtypes = [_c_p, _c_p, _c_p, _c_i, _c_d, _c_i, _c_i, ctypes.POINTER(GpCgInfo)]
     L.gp_cg_solve.restype = _c_i
+    L.gp_cg_solve_noalloc.argtypes = [_c_p, _c_p, _c_p, _c_i, _c_d, _c_i, _c_i, ctypes.POINTER(GpCgInfo)]
+    L.gp_cg_solve_noalloc.restype = _c_i
     L.gp_cg_solve_refined.argtypes = [_c_p, _c_p, _c_p, _c_p, _c_d, _c_d, _c_i, _c_i, _c_i,
                                       ctypes.POINTER(GpCgInfo)]
     L.gp_cg_solve_refined.restype = _c_i
@@ -345,6 +348,22 @@ class Plan:
         info = GpCgInfo()
         rc = load().gp_cg_solve(self._h, y.data_ptr(), alpha.data_ptr(), int(x0 is not None),
                                 float(tol), int(max_iter), int(replace_every), ctypes.byref(info))
+        if rc not in (GP_OK, GP_ENOCONV):
+            _check(rc)
+        return alpha, _info_dict(info)
+
+    def cg_solve_noalloc(self, y: torch.Tensor, alpha: torch.Tensor, tol: float = 1e-6,
+                         max_iter: int = 10000, use_x0: bool = False, replace_every: int = 0):
+        """gp_cg_solve_noalloc: the solve into the caller's `alpha` (initial guess
+        if use_x0), with no allocation in the library."""
+        y = _dev(y, "y")
+        if not (isinstance(alpha, torch.Tensor) and alpha.is_contiguous()):
+            raise TypeError("alpha must be a contiguous float64 CUDA tensor")
+        alpha = _dev(alpha, "alpha")
+        info = GpCgInfo()
+        rc = load().gp_cg_solve_noalloc(self._h, y.data_ptr(), alpha.data_ptr(), int(use_x0),
+                                        float(tol), int(max_iter), int(replace_every),
+                                        ctypes.byref(info))
         if rc not in (GP_OK, GP_ENOCONV):
             _check(rc)
         return alpha, _info_dict(info)
