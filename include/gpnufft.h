@@ -52,6 +52,11 @@ extern "C" {
 #define GP_EDEVICE (-6)     /* HIP runtime error */
 #define GP_EUNSUPPORTED (-7) /* parameters outside what the kernels support (e.g. n_f too large) */
 
+/* ------------------------------------------------------ spreading variants */
+#define GP_SPREAD_AUTO 0
+#define GP_SPREAD_LDS_ATOMIC 1
+#define GP_SPREAD_OWNER 2
+
 /* --------------------------------------------------------------- precision */
 #define GP_FP64 0           /* spread / FFT / mix / interpolate in fp64 */
 #define GP_FP32_BULK 1      /* spread / FFT / mix / interpolate in fp32; fp64 vectors and dots */
@@ -85,9 +90,11 @@ typedef struct {
   double box_lo[3], box_hi[3];
   double l_lo, l_hi;        /* widen the length-scale range (posterior targets); 0 = unused */
   size_t max_device_bytes;  /* admission limit for the plan's device memory; 0 = none */
-  int spread;               /* type-1 spreading: 0 = each thread owns grid cells and sums
-                               in registers (deterministic, default); 1 = per-(point, row)
-                               work items with LDS atomics */
+  int spread;               /* type-1 spreading variant (GP_SPREAD_*): 0 = automatic
+                               (GP_SPREAD_OWNER); 1 = per-(point, row) work items with LDS
+                               atomics; 2 = each thread owns grid cells of a tile (or, for
+                               fp32 grids in d >= 2, of a sub-tile with one wavefront each)
+                               and sums in registers in a fixed order (deterministic) */
   int interp;               /* type-2 interpolation: 0 = default (d = 2: 2x2-bin tiles plus
                                halo staged in LDS one grid pair at a time; d = 1, 3: as 2);
                                1 = one thread per point reading its window through the
@@ -126,7 +133,8 @@ typedef struct {
   double pred_tail;         /* predicted spectral-tail error of the Fourier box, relative */
   int m_capped;             /* 1 if M was limited by M_cap */
   int step3;                /* variant of step 3 in use (see gp_opts.step3) */
-  int spread;               /* spreading variant in use (see gp_opts.spread) */
+  int spread;               /* spreading variant in use: GP_SPREAD_LDS_ATOMIC or
+                               GP_SPREAD_OWNER (gp_opts.spread resolved) */
   int interp;               /* interpolation variant in use (see gp_opts.interp) */
   int64_t a_rows;           /* rows of the precomputed A table (distinct |n|^2) */
 } gp_plan_params;

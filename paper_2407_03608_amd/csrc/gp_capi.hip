@@ -225,7 +225,7 @@ static void fill_params(const Plan& P, gp_plan_params* o) {
   o->pred_tail = P.pred_tail;
   o->m_capped = P.m_capped;
   o->step3 = P.step3;
-  o->spread = P.spread_owner ? 0 : 1;
+  o->spread = P.spread_mode;
   o->interp = P.interp_mode;
   o->a_rows = P.a_rows;
 }

@@ -143,7 +143,7 @@ struct Plan {
   DevBuf etab;                // T [nt][nk][M+1]: exp(-tau_kj n^2) for dims >= 1
   DevBuf vtd;                 // T [nt] v~_j
   int step3 = 0;              // 0: radial precomputed A, 1: direct t-sum
-  int spread_owner = 1;       // 1: owner-computes spreading (no atomics), 0: LDS-atomic items
+  int spread_mode = GP_SPREAD_OWNER;  // resolved gp_opts.spread (never GP_SPREAD_AUTO)
   int interp_mode = 0;        // 0 default, 1 cache gather, 2 per-bin LDS tiles
   int64_t a_rows = 0;         // distinct |n|^2 values (rows of A)
   int nkp = 0;                // table width: nk rounded up to even

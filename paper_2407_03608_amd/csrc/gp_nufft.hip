@@ -78,7 +78,7 @@ __host__ __device__ constexpr int lds_stride(int rs) { return rs | 1; }
 // A crowded tile is split into chunks of its source points (work item
 // {tile, lo, hi, slot}); each chunk writes a partial tile to `part`, and
 // spread_reduce_kernel adds the partials in slot order.
-template <typename T, int D, int CPT>
+template <typename T, int D, int CPT, int GC>
 __global__ __launch_bounds__(kThreads) void spread_owner_kernel(
     NuArgs a, const double* __restrict__ x, const int* __restrict__ cell,
     const T* __restrict__ pw, int rs, const int* __restrict__ bin_start,
@@ -120,11 +120,11 @@ __global__ __launch_bounds__(kThreads) void spread_owner_kernel(
     cy[c] = D > 1 ? t0[1] + l % tc1 : 0;
     cz[c] = D > 2 ? t0[2] + l / tc1 : 0;
   }
-  V acc[CPT][kGC];
+  V acc[CPT][GC];
 #pragma unroll
   for (int c = 0; c < CPT; ++c)
 #pragma unroll
-    for (int g = 0; g < kGC; ++g) acc[c][g] = V{T(0), T(0)};
+    for (int g = 0; g < GC; ++g) acc[c][g] = V{T(0), T(0)};
 
   const int w = a.w;
   const int wko = D * w + 2 * a.g0;
@@ -220,11 +220,9 @@ __global__ __launch_bounds__(kThreads) void spread_owner_kernel(
             if (D > 1) v *= pr[w + d1];
             if (D > 2) v *= pr[2 * w + d2];
 #pragma unroll
-            for (int g = 0; g < kGC; ++g) {
-              if (g < a.gc) {
-                acc[c][g].x += v * pr[wko + 2 * g];
-                acc[c][g].y += v * pr[wko + 2 * g + 1];
-              }
+            for (int g = 0; g < GC; ++g) {
+              acc[c][g].x += v * pr[wko + 2 * g];
+              acc[c][g].y += v * pr[wko + 2 * g + 1];
             }
           }
         }
@@ -238,15 +236,13 @@ __global__ __launch_bounds__(kThreads) void spread_owner_kernel(
     if (slot >= 0) {
       const int l = threadIdx.x + c * kThreads;
 #pragma unroll
-      for (int g = 0; g < kGC; ++g)
-        if (g < a.gc) part[((int64_t)slot * a.slot_pairs + g) * tcells + l] = acc[c][g];
+      for (int g = 0; g < GC; ++g) part[((int64_t)slot * a.slot_pairs + g) * tcells + l] = acc[c][g];
       continue;
     }
     const int64_t gi = a.grid_off + (int64_t)cx[c] * a.gstride[0] + (int64_t)cy[c] * a.gstride[1] +
                        (int64_t)cz[c] * a.gstride[2];
 #pragma unroll
-    for (int g = 0; g < kGC; ++g)
-      if (g < a.gc) grid[(int64_t)(a.g0 + g) * a.pair_stride + gi] = acc[c][g];
+    for (int g = 0; g < GC; ++g) grid[(int64_t)(a.g0 + g) * a.pair_stride + gi] = acc[c][g];
   }
 }
 
@@ -295,7 +291,7 @@ __global__ __launch_bounds__(kThreads) void spread_reduce_kernel(
 // dimension and compacted by ballot; the summation order is the sorted order,
 // as in spread_owner_kernel.
 constexpr int kSubThreads = 64;
-template <typename T, int D>
+template <typename T, int D, int GC>
 __global__ __launch_bounds__(kSubThreads) void spread_sub_kernel(
     NuArgs a, int st, const double* __restrict__ x, const int* __restrict__ cell,
     const T* __restrict__ pw, int rs, const int* __restrict__ bin_start,
@@ -333,14 +329,17 @@ __global__ __launch_bounds__(kSubThreads) void spread_sub_kernel(
   }
   if (l != 0) mine = false;  // lanes beyond st^D own no cell
 
-  V acc[kGC];
+  V acc[GC];
 #pragma unroll
-  for (int g = 0; g < kGC; ++g) acc[g] = V{T(0), T(0)};
+  for (int g = 0; g < GC; ++g) acc[g] = V{T(0), T(0)};
   const int w = a.w;
   const int wko = D * w + 2 * a.g0;
   int nsrc_tot = 1;
   for (int r = 0; r < D; ++r) nsrc_tot *= a.nsrc;
-  // the concatenated source bins, as in spread_owner_kernel
+  // the concatenated source bins, as in spread_owner_kernel, without the bins
+  // none of whose points reach this sub-tile: along dimension r the points of
+  // the bin dq >= 1 tiles below start at most at t0 - (dq - 1) tile - 1, so
+  // their windows end before s0 when that start + w - 1 < s0
   int* s_sb0 = s_np + 1;           // [nsrc_tot]
   int* s_soff = s_sb0 + nsrc_tot;  // [nsrc_tot + 1]
   for (int sb = threadIdx.x; sb < nsrc_tot; sb += kSubThreads) {
@@ -348,9 +347,11 @@ __global__ __launch_bounds__(kSubThreads) void spread_sub_kernel(
     bool ok = true;
     int q = sb;
     for (int r = 0; r < D; ++r) {
-      const int br = tcoord[r] - (q % a.nsrc);
+      const int dq = q % a.nsrc;
+      const int br = tcoord[r] - dq;
       q /= a.nsrc;
       if (br < 0) ok = false;
+      if (dq > 0 && tcoord[r] * a.tile[r] - (dq - 1) * a.tile[r] - 1 + w - 1 < s0[r]) ok = false;
       b += (int64_t)br * mul;
       mul *= a.nbins[r];
     }
@@ -376,10 +377,9 @@ __global__ __launch_bounds__(kSubThreads) void spread_sub_kernel(
         int sb = 0;
         while (qpos >= s_soff[sb + 1]) ++sb;
         idx = s_sb0[sb] + (qpos - s_soff[sb]);
-        for (int r = 0; r < D; ++r) {
-          const int cr = cell[r * a.n + idx];
-          keep = keep && cr + w - 1 >= s0[r] && cr < s0[r] + st;
-        }
+        int cr[3];
+        for (int r = 0; r < D; ++r) cr[r] = cell[r * a.n + idx];  // all loads in flight
+        for (int r = 0; r < D; ++r) keep = keep & (cr[r] + w - 1 >= s0[r]) & (cr[r] < s0[r] + st);
       }
       const unsigned long long m = __ballot(keep);
       if (keep) s_map[__popcll(m & ((1ull << threadIdx.x) - 1ull))] = idx;
@@ -407,11 +407,10 @@ __global__ __launch_bounds__(kSubThreads) void spread_sub_kernel(
           T v = pr[d0] * s_x[p] * pr[w + d1];
           if (D > 2) v *= pr[2 * w + d2];
 #pragma unroll
-          for (int g = 0; g < kGC; ++g)
-            if (g < a.gc) {
-              acc[g].x += v * pr[wko + 2 * g];
-              acc[g].y += v * pr[wko + 2 * g + 1];
-            }
+          for (int g = 0; g < GC; ++g) {
+            acc[g].x += v * pr[wko + 2 * g];
+            acc[g].y += v * pr[wko + 2 * g + 1];
+          }
         }
       }
     }
@@ -420,8 +419,7 @@ __global__ __launch_bounds__(kSubThreads) void spread_sub_kernel(
   const int64_t gi = a.grid_off + (int64_t)c[0] * a.gstride[0] + (int64_t)c[1] * a.gstride[1] +
                      (int64_t)c[2] * a.gstride[2];
 #pragma unroll
-  for (int g = 0; g < kGC; ++g)
-    if (g < a.gc) grid[(int64_t)(a.g0 + g) * a.pair_stride + gi] = acc[g];
+  for (int g = 0; g < GC; ++g) grid[(int64_t)(a.g0 + g) * a.pair_stride + gi] = acc[g];
 }
 
 // ---------------------------------------------------------------- spread ----
@@ -903,6 +901,19 @@ size_t interp_smem(const Plan* P, int gc, int rs) {
          kPB * kGC * sizeof(double) + kPB * P->d * sizeof(int) + 16;
 }
 
+// Runs CALL(GCV) with GCV the compile-time pair count equal to gc (1..kGC).
+#define GP_GC_SWITCH(gc, CALL)                                  \
+  switch (gc) {                                                 \
+    case 1: CALL(1); break;                                     \
+    case 2: CALL(2); break;                                     \
+    case 3: CALL(3); break;                                     \
+    case 4: CALL(4); break;                                     \
+    case 5: CALL(5); break;                                     \
+    case 6: CALL(6); break;                                     \
+    case 7: CALL(7); break;                                     \
+    default: CALL(8); break;                                    \
+  }
+
 constexpr size_t kSmemCap = 64 * 1024;
 
 // Kernel arguments for the point set R (training points or targets) of plan P.
@@ -956,12 +967,14 @@ void launch_spread_owner(Plan* P, const Records& R, const double* xs) {
   for (int ch = 0; ch < nch; ++ch) {
     a.g0 = ch * gc;
     a.gc = std::min(gc, P->npair - a.g0);
-    hipLaunchKernelGGL((spread_owner_kernel<T, D, CPT>), dim3((unsigned)R.n_sp_work),
-                       dim3(kThreads), spread_owner_smem<T>(P, R.rs), P->stream, a, xs,
-                       R.cell.as<int>(), R.pw.as<T>(), R.rs, R.bin_start.as<int>(),
-                       R.n_sp_red > 0 ? R.sp_work.as<int4>() : nullptr,
-                       R.part.as<typename V2<T>::type>(),
-                       P->gridA.as<typename V2<T>::type>());
+#define GP_LAUNCH_OWNER(GCV)                                                                   \
+  hipLaunchKernelGGL((spread_owner_kernel<T, D, CPT, GCV>), dim3((unsigned)R.n_sp_work),         \
+                     dim3(kThreads), spread_owner_smem<T>(P, R.rs), P->stream, a, xs,            \
+                     R.cell.as<int>(), R.pw.as<T>(), R.rs, R.bin_start.as<int>(),                \
+                     R.n_sp_red > 0 ? R.sp_work.as<int4>() : nullptr,                            \
+                     R.part.as<typename V2<T>::type>(), P->gridA.as<typename V2<T>::type>())
+    GP_GC_SWITCH(a.gc, GP_LAUNCH_OWNER)
+#undef GP_LAUNCH_OWNER
     GP_CHECK_LAUNCH();
     if (R.n_sp_red > 0) {
       hipLaunchKernelGGL((spread_reduce_kernel<T, D>), dim3((unsigned)R.n_sp_red), dim3(kThreads), 0,
@@ -1042,10 +1055,13 @@ void launch_spread_sub(Plan* P, const Records& R, const double* xs, int st) {
   for (int ch = 0; ch < nch; ++ch) {
     a.g0 = ch * gc;
     a.gc = std::min(gc, P->npair - a.g0);
-    hipLaunchKernelGGL((spread_sub_kernel<T, D>), dim3((unsigned)(P->n_bins * nsub)),
-                       dim3(kSubThreads), smem, P->stream, a, st, xs, R.cell.as<int>(),
-                       R.pw.as<T>(), R.rs, R.bin_start.as<int>(),
-                       P->gridA.as<typename V2<T>::type>());
+#define GP_LAUNCH_SUB(GCV)                                                                    \
+  hipLaunchKernelGGL((spread_sub_kernel<T, D, GCV>), dim3((unsigned)(P->n_bins * nsub)),        \
+                     dim3(kSubThreads), smem, P->stream, a, st, xs, R.cell.as<int>(),           \
+                     R.pw.as<T>(), R.rs, R.bin_start.as<int>(),                                 \
+                     P->gridA.as<typename V2<T>::type>())
+    GP_GC_SWITCH(a.gc, GP_LAUNCH_SUB)
+#undef GP_LAUNCH_SUB
     GP_CHECK_LAUNCH();
   }
 }
@@ -1053,15 +1069,16 @@ void launch_spread_sub(Plan* P, const Records& R, const double* xs, int st) {
 template <typename T>
 void spread_dispatch(Plan* P, const Records& R, const double* xs) {
   const int tcells = P->tile[0] * P->tile[1] * P->tile[2];
+  const int mode = P->spread_mode;
   // fp32 grids in d >= 2: one wavefront per sub-tile (measured 4-7 % faster
   // there; 2x slower for fp64, whose 16-byte rows make the staging dominate)
-  if (P->spread_owner && P->d >= 2 && P->precision == GP_FP32_BULK) {
+  if (mode != GP_SPREAD_LDS_ATOMIC && P->d >= 2 && P->precision == GP_FP32_BULK) {
     const int st = std::min(P->d == 2 ? 8 : 4, P->tile[0]);
     if (P->d == 2) launch_spread_sub<T, 2>(P, R, xs, st);
     else launch_spread_sub<T, 3>(P, R, xs, st);
     return;
   }
-  if (P->spread_owner && tcells <= 2 * kThreads) {
+  if (mode != GP_SPREAD_LDS_ATOMIC && tcells <= 2 * kThreads) {
     const bool two = tcells > kThreads;
     if (P->d == 1) two ? launch_spread_owner<T, 1, 2>(P, R, xs) : launch_spread_owner<T, 1, 1>(P, R, xs);
     else if (P->d == 2) two ? launch_spread_owner<T, 2, 2>(P, R, xs) : launch_spread_owner<T, 2, 1>(P, R, xs);

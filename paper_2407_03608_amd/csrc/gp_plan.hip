@@ -953,7 +953,8 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
 
   // ---- step 3 variant; radial rows of the precomputed tensor
   P->step3 = opts.step3 ? 1 : 0;
-  P->spread_owner = opts.spread ? 0 : 1;
+  if (opts.spread < 0 || opts.spread > 2) throw Error{GP_EINVAL, "opts.spread must be 0, 1 or 2"};
+  P->spread_mode = opts.spread != GP_SPREAD_AUTO ? opts.spread : GP_SPREAD_OWNER;
   if (opts.interp < 0 || opts.interp > 2) throw Error{GP_EINVAL, "opts.interp must be 0, 1 or 2"};
   P->interp_mode = opts.interp;
   P->nkp = P->nk + (P->nk & 1);
