@@ -232,6 +232,55 @@ def secondary_workloads(gp, torch, args):
         "plan_seconds": round(tp, 3),
         "plan": {k: info[k] for k in ("n_sigma", "n_t", "dw", "M", "nf", "w", "upsample", "na", "n_pairs", "device_bytes")}}
     P.close()
+    del X, S, L, Y
+    out["multi_rhs_cg"] = multi_rhs_leg(gp, torch, inputs)
+    return out
+
+
+def multi_rhs_leg(gp, torch, inputs, m=16):
+    """Solves for m right-hand sides on one plan, as in the posterior
+    covariance (eq:postcov): d=2, N=1e5, nu=5/2, l in [0.03, 0.06], eta=0.3,
+    fp64 tol 1e-8, CG to 1e-6.  Block CG (gp_cg_solve_multi, block = 1: one
+    Krylov space, each operator application shared by the block) and lockstep
+    multi-right-hand-side CG (block = 0) against m sequential gp_cg_solve
+    calls; then gp_posterior_cov at m targets (block CG inside)."""
+    import numpy as np
+    log("secondary: multi-right-hand-side CG")
+    p = inputs.random_small(2, 100_000, seed=12, nu=2.5, lmin=0.03, lmax=0.06, eta=0.3)
+    X, S, L = (torch.as_tensor(v).to("cuda") for v in (p.x, p.sigma, p.l))
+    P = gp.Plan(X, S, L, p.nu, p.eta, 1e-8)
+    Y = torch.as_tensor(np.random.default_rng(3).standard_normal((m, p.n))).to("cuda")
+    P.cg_solve_multi(Y[:2], tol=1e-6, max_iter=20000)  # warm-up (allocates the batched grids)
+    out = {"workload": f"d=2 N=1e5 uniform, nu=5/2, l in [0.03,0.06], eta=0.3, fp64 tol 1e-8, "
+                       f"{m} random right-hand sides, CG to 1e-6", "m": m}
+    for name, blk in (("block", True), ("lockstep", False)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        A, its, rels, info = P.cg_solve_multi(Y, tol=1e-6, max_iter=20000, block=blk)
+        torch.cuda.synchronize()
+        out[name] = {"seconds": round(time.perf_counter() - t0, 3), "iters": its[0] if blk else its,
+                     "worst_rel_res": info["rel_res"], "status": info["status"]}
+    t0 = time.perf_counter()
+    its1 = []
+    for j in range(m):
+        _, ci = P.cg_solve(Y[j].contiguous(), tol=1e-6, max_iter=20000)
+        its1.append(ci["iters"])
+    torch.cuda.synchronize()
+    out["serial"] = {"seconds": round(time.perf_counter() - t0, 3), "iters": its1}
+    out["block_speedup_vs_serial"] = round(out["serial"]["seconds"] / out["block"]["seconds"], 2)
+    rng = np.random.default_rng(5)
+    xt = torch.as_tensor(rng.uniform(0.05, 0.95, size=(m, 2))).to("cuda")
+    lt = torch.as_tensor(rng.uniform(p.l.min(), p.l.max(), size=m)).to("cuda")
+    st = torch.as_tensor(rng.uniform(0.8, 1.2, size=m)).to("cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, var, ci = P.posterior_cov(xt, st, lt, tol=1e-6, max_iter=20000)
+    torch.cuda.synchronize()
+    out["posterior_cov"] = {"targets": m, "seconds": round(time.perf_counter() - t0, 3),
+                            "block_iters": ci["iters"], "status": ci["status"]}
+    inf = P.info()
+    out["plan"] = {"M": inf["M"], "nf": inf["nf"][0], "n_pairs": inf["n_pairs"]}
+    P.close()
     return out
 
 

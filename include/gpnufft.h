@@ -217,12 +217,38 @@ int gp_cg_solve_refined(gp_plan_t inner, gp_plan_t outer, const double* y, doubl
 int gp_posterior_mean(gp_plan_t plan, const double* alpha, int64_t m, const double* targets,
                       const double* sigma_t, const double* l_t, double* mu);
 
+/* Conjugate gradients for m right-hand sides at once (eq:gprsolve with m
+ * observation vectors, e.g. the columns of eq:postcov): column j of y and
+ * alpha (device fp64, caller order) starts at y + j n; alpha = 0 initially.
+ * Stops when every column has relative residual <= tol, or after max_iter
+ * iterations.  Every iteration applies the operator to all the search
+ * directions at once: each column's spreading and interpolation, then one FFT
+ * batch over all columns' grids and one pass of step 3 that reads each row of
+ * its table once for all columns.
+ *  block = 0: m CG recurrences in lockstep, each with its own step lengths and
+ *    stopping test: each column's iterates and iteration count are bit for bit
+ *    those of gp_cg_solve on that column (replace_every = 0).
+ *  block = 1: block CG (O'Leary 1980) over blocks of up to 16 columns, the
+ *    columns sharing one Krylov space (fewer iterations than separate solves);
+ *    the search block is kept orthonormal by a pivoted Cholesky QR of its
+ *    unit-scaled columns that drops directions below 1e-6 (deflation: exactly
+ *    or nearly dependent columns share directions).
+ * Columns are processed in blocks whose batched grids fit in half of the free
+ * device memory.  iters, rel_res: host arrays of m entries (iterations of the
+ * column's recurrence or block; final relative residual), or NULL.  info: the
+ * largest iteration count, the worst final relative residual, GP_ENOCONV if
+ * any column stopped at max_iter (alpha is then still written). */
+int gp_cg_solve_multi(gp_plan_t plan, int m, const double* y, double* alpha, double tol,
+                      int max_iter, int block, int* iters, double* rel_res, gp_cg_info* info);
+
 /* Posterior covariance eq:postcov at m targets (m x d device fp64, scales
  * sigma_t, l_t as for gp_posterior_mean):
  *   Sigma(x*_i, x*_j) = K~(x*_i, x*_j) - K~(x*_i, X) (K~ + eta^2 I)^{-1} K~(X, x*_j),
  * every term with the plan's operator K~ (so Sigma is the Schur complement of
- * a positive semidefinite matrix).  One CG solve per target (tolerance tol,
- * at most max_iter iterations each) plus two operator applications.
+ * a positive semidefinite matrix).  The solves (K~ + eta^2 I)^{-1} K~(X, x*_j)
+ * run as block CG (gp_cg_solve_multi with block = 1) over blocks of up to 16
+ * targets (tolerance tol, at most max_iter iterations per block), plus two
+ * operator applications per target.
  * cov: m x m row-major device fp64 (column j from solve j; symmetric up to the
  * CG tolerance), or NULL; var: the m variances Sigma(x*_j, x*_j), or NULL (not
  * both NULL).  info: total iterations over the solves, the worst final

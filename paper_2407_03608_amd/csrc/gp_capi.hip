@@ -1,10 +1,12 @@
 // C ABI of gpnufft (declarations and contracts in include/gpnufft.h).
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "gp_internal.h"
 
@@ -342,6 +344,54 @@ int gp_cg_solve_refined(gp_plan_t hin, gp_plan_t hout, const double* y, double* 
   });
 }
 
+int gp_cg_solve_multi(gp_plan_t h, int m, const double* y, double* alpha, double tol, int max_iter,
+                      int block, int* iters, double* rel_res, gp_cg_info* info) {
+  return guarded([&] {
+    if (!h || !y || !alpha) throw Error{GP_EINVAL, "null argument"};
+    if (m < 1) throw Error{GP_EINVAL, "m must be >= 1"};
+    if (!(tol > 0) || max_iter < 0) throw Error{GP_EINVAL, "tol must be > 0, max_iter >= 0"};
+    Plan* P = &h->P;
+    const auto t0 = std::chrono::steady_clock::now();
+    const int64_t n = P->n;
+    hipStream_t s = P->stream;
+    if (block != 0 && block != 1) throw Error{GP_EINVAL, "block must be 0 or 1"};
+    int mb = multi_capacity(P, block ? std::min(m, 16) : m);
+    DevBuf bs, xs;
+    bs.alloc((size_t)mb * n * sizeof(double));
+    xs.alloc((size_t)mb * n * sizeof(double));
+    std::vector<int> it(m);
+    std::vector<double> rr(m);
+    int status = GP_OK;
+    for (int j0 = 0; j0 < m; j0 += mb) {
+      const int nb = std::min(mb, m - j0);
+      for (int j = 0; j < nb; ++j) {
+        gather_sorted(P, y + (int64_t)(j0 + j) * n, bs.as<double>() + (int64_t)j * n);
+        zero_sorted(P, xs.as<double>() + (int64_t)j * n);
+      }
+      const int st = block ? cg_block_sorted(P, nb, bs.as<double>(), xs.as<double>(), tol,
+                                             max_iter, it.data() + j0, rr.data() + j0)
+                           : cg_multi_sorted(P, nb, bs.as<double>(), xs.as<double>(), tol,
+                                             max_iter, it.data() + j0, rr.data() + j0);
+      if (st != GP_OK) status = st;
+      for (int j = 0; j < nb; ++j)
+        scatter_user(P, xs.as<double>() + (int64_t)j * n, alpha + (int64_t)(j0 + j) * n);
+    }
+    GP_HIP(hipStreamSynchronize(s));
+    if (iters) for (int j = 0; j < m; ++j) iters[j] = it[j];
+    if (rel_res) for (int j = 0; j < m; ++j) rel_res[j] = rr[j];
+    if (info) {
+      info->iters = *std::max_element(it.begin(), it.end());
+      info->status = status;
+      info->rel_res = *std::max_element(rr.begin(), rr.end());
+      info->rel_res_true = -1.0;
+      info->refinements = 0;
+      info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (status != GP_OK) set_error("a column reached max_iter before the tolerance");
+    return status;
+  });
+}
+
 // Targets must lie in the plan's box and length-scale range (host check).
 static void validate_targets(Plan* P, int64_t m, const double* targets, const double* sigma_t,
                              const double* l_t) {
@@ -416,39 +466,50 @@ int gp_posterior_cov(gp_plan_t h, int64_t m, const double* targets, const double
     GP_HIP(hipStreamSynchronize(s));
     for (int64_t q = 0; q < m; ++q) inv[perm[q]] = (int)q;
     const int64_t n = P->n;
+    // targets in blocks of mb: the block's right-hand sides k_j = K~(X, x*_j)
+    // are solved together by one multi-right-hand-side CG (each operator
+    // application shared by the block)
+    const int mb = multi_capacity(P, (int)std::min<int64_t>(m, 16));
     DevBuf e, prior, cross, kb, vb;
     e.alloc(m * sizeof(double));
-    prior.alloc(m * sizeof(double));
+    prior.alloc((size_t)mb * m * sizeof(double));
     cross.alloc(m * sizeof(double));
-    kb.alloc(n * sizeof(double));
-    vb.alloc(n * sizeof(double));
-    const unsigned mb = (unsigned)((m + 255) / 256);
+    kb.alloc((size_t)mb * n * sizeof(double));
+    vb.alloc((size_t)mb * n * sizeof(double));
+    const unsigned mblk = (unsigned)((m + 255) / 256);
     int64_t total = 0;
     double worst = 0.0;
     int status = GP_OK;
-    for (int64_t j = 0; j < m; ++j) {
-      // k_j = K~(X, x*_j) and the prior column K~(X*, x*_j) from one forward pass
-      hipLaunchKernelGGL(unit_vector_kernel, dim3(mb), dim3(256), 0, s, m, (int64_t)inv[j],
-                         e.as<double>());
-      GP_CHECK_LAUNCH();
-      forward_from(P, T, e.as<double>());
-      interp_from_grid(P, P->rec, kb.as<double>());
-      interp_from_grid(P, T, prior.as<double>());
-      // v_j = (K~ + eta^2 I)^{-1} k_j
-      GP_HIP(hipMemsetAsync(vb.p, 0, n * sizeof(double), s));
-      int it = 0;
-      double rel = 0.0;
-      const int st = cg_solve_sorted(P, kb.as<double>(), vb.as<double>(), true, tol, max_iter, 0,
-                                     &it, &rel);
-      total += it;
-      worst = std::max(worst, rel);
+    std::vector<int> it(mb);
+    std::vector<double> rel(mb);
+    for (int64_t j0 = 0; j0 < m; j0 += mb) {
+      const int nb = (int)std::min<int64_t>(mb, m - j0);
+      for (int q = 0; q < nb; ++q) {
+        const int64_t j = j0 + q;
+        // k_j = K~(X, x*_j) and the prior column K~(X*, x*_j) from one forward pass
+        hipLaunchKernelGGL(unit_vector_kernel, dim3(mblk), dim3(256), 0, s, m, (int64_t)inv[j],
+                           e.as<double>());
+        GP_CHECK_LAUNCH();
+        forward_from(P, T, e.as<double>());
+        interp_from_grid(P, P->rec, kb.as<double>() + (int64_t)q * n);
+        interp_from_grid(P, T, prior.as<double>() + (int64_t)q * m);
+        zero_sorted(P, vb.as<double>() + (int64_t)q * n);
+      }
+      // v_j = (K~ + eta^2 I)^{-1} k_j for the block, by block CG
+      const int st = cg_block_sorted(P, nb, kb.as<double>(), vb.as<double>(), tol, max_iter,
+                                     it.data(), rel.data());
       if (st != GP_OK) status = st;
-      // cross term K~(X*, X) v_j
-      forward_from(P, P->rec, vb.as<double>());
-      interp_from_grid(P, T, cross.as<double>());
-      hipLaunchKernelGGL(cov_column_kernel, dim3(mb), dim3(256), 0, s, m, T.perm.as<int>(),
-                         prior.as<double>(), cross.as<double>(), j, cov, var);
-      GP_CHECK_LAUNCH();
+      for (int q = 0; q < nb; ++q) {
+        const int64_t j = j0 + q;
+        total += it[q];
+        worst = std::max(worst, rel[q]);
+        // cross term K~(X*, X) v_j
+        forward_from(P, P->rec, vb.as<double>() + (int64_t)q * n);
+        interp_from_grid(P, T, cross.as<double>());
+        hipLaunchKernelGGL(cov_column_kernel, dim3(mblk), dim3(256), 0, s, m, T.perm.as<int>(),
+                           prior.as<double>() + (int64_t)q * m, cross.as<double>(), j, cov, var);
+        GP_CHECK_LAUNCH();
+      }
     }
     GP_HIP(hipStreamSynchronize(s));
     if (info) {

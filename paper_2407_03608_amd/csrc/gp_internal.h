@@ -153,6 +153,18 @@ struct Plan {
   DevBuf tw[3];               // FFT twiddles per distinct length (T complex)
   DevBuf tw4;                 // four-step twiddles (1-D, T complex, length nf)
   DevBuf gridA, gridB, gridB2, gridC;
+  int64_t grid_elems[4] = {0, 0, 0, 0};  // complex elements per grid pair of A, B, B2, C
+  // The grids the matvec kernels read and write: the plan's own (one set), or
+  // the batched grids of a multi-vector application, `nsets` consecutive sets
+  // of npair pairs each.  Spreading and interpolation work on set `cur`; the
+  // FFT passes and step 3 on all sets at once.
+  struct GridView {
+    void *A = nullptr, *B = nullptr, *B2 = nullptr, *C = nullptr;
+    int nsets = 1;
+    int cur = 0;
+  } gv;
+  DevBuf mA, mB, mB2, mC;     // batched grids for up to m_cap vectors (allocated on first use)
+  int m_cap = 0;
   DevBuf vec;                 // fp64 scratch vectors for matvec / CG (sorted order)
   // CG reductions (allocated once per plan): per-block partial sums, the
   // scalar slots of the solver and a pinned host mirror of those slots
@@ -200,6 +212,13 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
 
 // nufft.hip: y = K~ x (+ eta^2 x) with x, y fp64 in SORTED order on the plan stream.
 void matvec_sorted(Plan* P, const double* x_sorted, double* y_sorted, int add_noise);
+// The same for m vectors at once (x, y: m consecutive sorted-order vectors of
+// length n), sharing each FFT pass and the step-3 table reads: the result for
+// every vector has the same bits as matvec_sorted gives it.  Uses batched
+// grids for up to `m` vectors (allocated on first use; GP_ENOMEM if they do not fit).
+void matvec_multi_sorted(Plan* P, int m, const double* x_sorted, double* y_sorted, int add_noise);
+// Largest m for which the batched grids fit in half of the free device memory.
+int multi_capacity(Plan* P, int want);
 // Evaluate the type-2 + combine step at arbitrary mapped targets after a forward
 // pass of x_sorted; used by the posterior mean.
 void posterior_sorted(Plan* P, const double* x_sorted, int64_t m, const double* tpts,
@@ -236,6 +255,13 @@ int cg_solve_sorted_with(Plan* P, const CgScratch& sc, const double* b, double* 
 int cg_solve_sorted(Plan* P, const double* b, double* x, bool x_zero, double tol, int max_iter,
                     int replace_every, int* iters, double* rel_res);
 double dot_sorted(Plan* P, const double* a, const double* b, int64_t n);
+// CG for m right-hand sides in lockstep, sharing each operator application
+// (b, x: m consecutive sorted vectors, x = 0 on entry; iters, rel: host, m)
+int cg_multi_sorted(Plan* P, int m, const double* b, double* x, double tol, int max_iter,
+                    int* iters, double* rel);
+// block CG (shared Krylov space) for 1..16 right-hand sides, same layout
+int cg_block_sorted(Plan* P, int m, const double* b, double* x, double tol, int max_iter,
+                    int* iters, double* rel);
 // refinement with two plans on the same points, vectors in caller order (capi.hip)
 int cg_refined_user(Plan* Pi, Plan* Po, const double* y, double* alpha, double tol,
                     double inner_tol, int max_iter, int max_refine, int replace_every,

@@ -120,6 +120,8 @@ struct RadialArgs {
   int64_t pair_stride;
   int fourstep;
   int64_t nf, L1, L2;
+  int nsets;              // vector sets (consecutive, set_stride elements apart)
+  int64_t set_stride;
 };
 
 __device__ __forceinline__ int64_t radial_store(const RadialArgs& a, const int64_t* nv) {
@@ -165,9 +167,12 @@ __global__ __launch_bounds__(kThreads) void mode_radial_kernel(
       break;
     }
   // Sign patterns are processed two at a time so that one pass over the row of
-  // A serves both (the row is the dominant read of this kernel).
+  // A serves both (the row is the dominant read of this kernel); the vector
+  // sets of a multi-vector application reuse the row from the caches.
   const int npat = 1 << (a.d - 1);
+  for (int set = 0; set < a.nsets; ++set)
   for (int pg = 0; pg < npat; pg += 2) {
+    V* __restrict__ Cs = C + set * a.set_stride;
     bool keep[2];
     int64_t st0[2], st1[2];
 #pragma unroll
@@ -192,8 +197,8 @@ __global__ __launch_bounds__(kThreads) void mode_radial_kernel(
       for (int g = 0; g < NK / 2; ++g) {
         V z = V{T(0), T(0)}, zc = V{T(0), T(0)};
         if (keep[h] && g < a.npair) {
-          z = C[g * a.pair_stride + st0[h]];
-          zc = C[g * a.pair_stride + st1[h]];
+          z = Cs[g * a.pair_stride + st0[h]];
+          zc = Cs[g * a.pair_stride + st1[h]];
         }
         b[h][2 * g] = V{T(0.5) * (z.x + zc.x) * D, T(0.5) * (z.y - zc.y) * D};
         b[h][2 * g + 1] = V{T(0.5) * (z.y + zc.y) * D, T(-0.5) * (z.x - zc.x) * D};
@@ -228,8 +233,8 @@ __global__ __launch_bounds__(kThreads) void mode_radial_kernel(
         if (g >= a.npair) break;
         const V pp = V{acc[h][2 * g].x * D, acc[h][2 * g].y * D};
         const V qq = V{acc[h][2 * g + 1].x * D, acc[h][2 * g + 1].y * D};
-        C[g * a.pair_stride + st0[h]] = V{pp.x - qq.y, pp.y + qq.x};
-        if (st1[h] != st0[h]) C[g * a.pair_stride + st1[h]] = V{pp.x + qq.y, -pp.y + qq.x};
+        Cs[g * a.pair_stride + st0[h]] = V{pp.x - qq.y, pp.y + qq.x};
+        if (st1[h] != st0[h]) Cs[g * a.pair_stride + st1[h]] = V{pp.x + qq.y, -pp.y + qq.x};
       }
     }
   }
@@ -320,10 +325,13 @@ void launch_mode_nk(Plan* P) {
   a.L2 = P->L2;
   a.pair_stride = P->fourstep ? P->nf[0] : a.F;
   const int64_t half = (a.F + 1) / 2;
-  hipLaunchKernelGGL((mode_kernel<T, NK>), dim3((unsigned)((half + kThreads - 1) / kThreads)),
-                     dim3(kThreads), 0, P->stream, a, P->gridC.as<typename V2<T>::type>(),
-                     P->gtab.as<T>(), P->etab.as<T>(), P->vtd.as<T>(), P->dec.as<T>());
-  GP_CHECK_LAUNCH();
+  for (int set = 0; set < P->gv.nsets; ++set) {
+    hipLaunchKernelGGL((mode_kernel<T, NK>), dim3((unsigned)((half + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, P->stream, a,
+                       static_cast<typename V2<T>::type*>(P->gv.C) + set * P->npair * a.pair_stride,
+                       P->gtab.as<T>(), P->etab.as<T>(), P->vtd.as<T>(), P->dec.as<T>());
+    GP_CHECK_LAUNCH();
+  }
 }
 
 template <typename T, int NK>
@@ -343,16 +351,21 @@ void launch_radial_nk(Plan* P) {
   int64_t F = 1;
   for (int r = 0; r < P->d; ++r) F *= a.mc;
   a.pair_stride = P->fourstep ? P->nf[0] : F;
+  a.nsets = P->gv.nsets;
+  a.set_stride = P->npair * a.pair_stride;
+  auto* C = static_cast<typename V2<T>::type*>(P->gv.C);
   if (P->d == 1) {
     constexpr int PPB = kThreads / NK;
-    hipLaunchKernelGGL((mode_radial_1d_kernel<T, NK>), dim3((unsigned)((a.Q + PPB - 1) / PPB)),
-                       dim3(kThreads), 0, P->stream, a, P->gridC.as<typename V2<T>::type>(),
-                       P->atab.as<T>(), P->dec.as<T>());
-    GP_CHECK_LAUNCH();
+    for (int set = 0; set < a.nsets; ++set) {
+      hipLaunchKernelGGL((mode_radial_1d_kernel<T, NK>), dim3((unsigned)((a.Q + PPB - 1) / PPB)),
+                         dim3(kThreads), 0, P->stream, a, C + set * a.set_stride,
+                         P->atab.as<T>(), P->dec.as<T>());
+      GP_CHECK_LAUNCH();
+    }
     return;
   }
   hipLaunchKernelGGL((mode_radial_kernel<T, NK>), dim3((unsigned)((a.Q + kThreads - 1) / kThreads)),
-                     dim3(kThreads), 0, P->stream, a, P->gridC.as<typename V2<T>::type>(),
+                     dim3(kThreads), 0, P->stream, a, C,
                      P->atab.as<T>(), P->d > 1 ? P->rowidx.as<int>() : nullptr, P->dec.as<T>());
   GP_CHECK_LAUNCH();
 }
@@ -397,10 +410,11 @@ void GP_MIX_FN(Plan* P) {
   using T = GP_MODE_T;
   launch_mode<T>(P);
   if (P->fourstep) {
-    const int64_t tot = (int64_t)P->nf[0] * P->npair;
+    const int npairs = P->npair * P->gv.nsets;
+    const int64_t tot = (int64_t)P->nf[0] * npairs;
     hipLaunchKernelGGL(zero_band_kernel<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
-                       P->stream, P->gridC.as<typename V2<T>::type>(), (int64_t)P->nf[0],
-                       (int64_t)P->L1, (int64_t)P->L2, P->M, P->npair);
+                       P->stream, static_cast<typename V2<T>::type*>(P->gv.C), (int64_t)P->nf[0],
+                       (int64_t)P->L1, (int64_t)P->L2, P->M, npairs);
     GP_CHECK_LAUNCH();
   }
 }

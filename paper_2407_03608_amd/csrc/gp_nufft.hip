@@ -716,8 +716,11 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(
 // order of every sum is fixed.  The next pair's tile is loaded into registers
 // while the current pair is computed (the kernel is otherwise latency-bound:
 // 1.71 -> 0.88 ms at d=2 N=1e6 fp64 on the 8192^2 grid).
-constexpr int kPB2 = 128;                                   // points staged per batch
-constexpr int kNI2 = (kPB2 * kRG + kThreads - 1) / kThreads;  // items per thread
+// Points staged per batch: 128 in 2-D; 320 for fp32 grids in 3-D, whose 2x2x1
+// block (20 x 20 x 12 cells at w = 5) is then staged once per 320 points
+// instead of per 128 (the block and the rows still fit 80 KB).
+template <int D, typename T>
+constexpr int kPB2 = (D > 2 && sizeof(T) == 4) ? 320 : 128;
 
 // tile cells per thread kept in flight by the pipelined variant (a d=3 block
 // of 2x2x1 bins of 8^3 cells with w = 5 has 20 x 20 x 12 = 4800 cells)
@@ -730,6 +733,8 @@ __global__ __launch_bounds__(kThreads) void interp_super_kernel(
     const T* __restrict__ pw, int rs, const int* __restrict__ bin_start,
     const int4* __restrict__ work, const double* __restrict__ x, double* __restrict__ y) {
   using V = typename V2<T>::type;
+  constexpr int PB = kPB2<D, T>;
+  constexpr int NI = (PB * kRG + kThreads - 1) / kThreads;  // items per thread
   extern __shared__ __align__(16) unsigned char smem[];
   const int w = a.w;
   // blocks of 2 x 2 (x 1) bins: the first two dimensions doubled
@@ -738,9 +743,9 @@ __global__ __launch_bounds__(kThreads) void interp_super_kernel(
   const int ps0 = pc0 | 1;  // odd row stride: the RG lanes of a point hit different banks
   const int ls = lds_stride(rs);
   V* tile = reinterpret_cast<V*>(smem);                              // [pc2][pc1][ps0]
-  T* s_rec = reinterpret_cast<T*>(tile + (size_t)ps0 * pc1 * pc2);   // [kPB2][ls]
-  int* s_cell = reinterpret_cast<int*>(s_rec + kPB2 * ls);           // [kPB2][D]
-  int* s_idx = s_cell + D * kPB2;                                     // [kPB2] sorted index
+  T* s_rec = reinterpret_cast<T*>(tile + (size_t)ps0 * pc1 * pc2);   // [PB][ls]
+  int* s_cell = reinterpret_cast<int*>(s_rec + PB * ls);           // [PB][D]
+  int* s_idx = s_cell + D * PB;                                     // [PB] sorted index
 
   const int4 wk = work[blockIdx.x];
   const int nsb0 = (a.nbins[0] + 1) / 2, nsb1 = (a.nbins[1] + 1) / 2;
@@ -758,8 +763,8 @@ __global__ __launch_bounds__(kThreads) void interp_super_kernel(
   const int cellsw = D > 2 ? w * w : w;  // window rows per point
   const int RG = cellsw >= kRG ? kRG : (cellsw >= 2 ? 2 : 1);  // power of two; kThreads % RG == 0
   const int wko = D * w;
-  for (int pos = wk.y; pos < wk.z; pos += kPB2) {
-    const int np = min(kPB2, wk.z - pos);
+  for (int pos = wk.y; pos < wk.z; pos += PB) {
+    const int np = min(PB, wk.z - pos);
     __syncthreads();
     for (int e = threadIdx.x; e < np; e += kThreads) {
       const int q = pos + e;
@@ -774,9 +779,9 @@ __global__ __launch_bounds__(kThreads) void interp_super_kernel(
       const int p = e / rs, c = e - p * rs;
       s_rec[p * ls + c] = pw[(int64_t)s_idx[p] * rs + c];
     }
-    double part[kNI2];
+    double part[NI];
 #pragma unroll
-    for (int k = 0; k < kNI2; ++k) part[k] = 0.0;
+    for (int k = 0; k < NI; ++k) part[k] = 0.0;
     const int nitems = np * RG;
     const int ucells = pc0 * pc1 * pc2;
     // PIPE: the next pair's tile is loaded into registers while this pair is
@@ -831,7 +836,7 @@ __global__ __launch_bounds__(kThreads) void interp_super_kernel(
       }
       __syncthreads();
 #pragma unroll
-      for (int k = 0; k < kNI2; ++k) {
+      for (int k = 0; k < NI; ++k) {
         const int it = threadIdx.x + k * kThreads;
         if (it < nitems) {
           const int rg = it % RG, p = it / RG;
@@ -862,7 +867,7 @@ __global__ __launch_bounds__(kThreads) void interp_super_kernel(
       }
     }
 #pragma unroll
-    for (int k = 0; k < kNI2; ++k) {
+    for (int k = 0; k < NI; ++k) {
       const int it = threadIdx.x + k * kThreads;  // a lane group is all in or all out
       double v = part[k];
       if (RG >= 2) v += __shfl_xor(v, 1);
@@ -949,6 +954,20 @@ NuArgs nu_args(const Plan* P, const Records& R) {
   return a;
 }
 
+// Grid A (spread output, interpolation input) of the current vector set.
+template <typename V>
+V* cur_gridA(const Plan* P) {
+  const int64_t set = (int64_t)P->npair * P->grid_elems[0];
+  return static_cast<V*>(P->gv.A) + P->gv.cur * set;
+}
+// The 1-D four-step leaves the inverse transform in grid C.
+template <typename V>
+V* cur_interp_grid(const Plan* P) {
+  if (!P->fourstep) return cur_gridA<V>(P);
+  const int64_t set = (int64_t)P->npair * P->grid_elems[3];
+  return static_cast<V*>(P->gv.C) + P->gv.cur * set;
+}
+
 template <typename T>
 size_t spread_owner_smem(const Plan* P, int rs) {
   static_assert(kPB == 64, "the spread pre-filter compacts one batch per wavefront");
@@ -972,14 +991,14 @@ void launch_spread_owner(Plan* P, const Records& R, const double* xs) {
                      dim3(kThreads), spread_owner_smem<T>(P, R.rs), P->stream, a, xs,            \
                      R.cell.as<int>(), R.pw.as<T>(), R.rs, R.bin_start.as<int>(),                \
                      R.n_sp_red > 0 ? R.sp_work.as<int4>() : nullptr,                            \
-                     R.part.as<typename V2<T>::type>(), P->gridA.as<typename V2<T>::type>())
+                     R.part.as<typename V2<T>::type>(), cur_gridA<typename V2<T>::type>(P))
     GP_GC_SWITCH(a.gc, GP_LAUNCH_OWNER)
 #undef GP_LAUNCH_OWNER
     GP_CHECK_LAUNCH();
     if (R.n_sp_red > 0) {
       hipLaunchKernelGGL((spread_reduce_kernel<T, D>), dim3((unsigned)R.n_sp_red), dim3(kThreads), 0,
                          P->stream, a, R.sp_red.as<int4>(), R.part.as<typename V2<T>::type>(),
-                         P->gridA.as<typename V2<T>::type>());
+                         cur_gridA<typename V2<T>::type>(P));
       GP_CHECK_LAUNCH();
     }
   }
@@ -998,7 +1017,7 @@ void launch_spread(Plan* P, const Records& R, const double* xs) {
     hipLaunchKernelGGL((spread_kernel<T, D>), dim3((unsigned)P->n_bins), dim3(kThreads),
                        spread_smem<T>(P, a.gc, R.rs), P->stream, a, xs, R.cell.as<int>(),
                        R.pw.as<T>(), R.rs, R.bin_start.as<int>(),
-                       P->gridA.as<typename V2<T>::type>());
+                       cur_gridA<typename V2<T>::type>(P));
     GP_CHECK_LAUNCH();
   }
 }
@@ -1029,7 +1048,7 @@ void launch_interp(Plan* P, const Records& R, const double* xs, double* ys, int 
   while (gc > 1 && interp_smem<T>(P, gc, R.rs) > kSmemCap) --gc;
   const int nch = (P->npair + gc - 1) / gc;
   // the 1-D four-step inverse leaves the grid in C (see fft_all)
-  const DevBuf& g = P->fourstep ? P->gridC : P->gridA;
+  const auto* gptr = cur_interp_grid<typename V2<T>::type>(P);
   for (int ch = 0; ch < nch; ++ch) {
     a.g0 = ch * gc;
     a.gc = std::min(gc, P->npair - a.g0);
@@ -1037,7 +1056,7 @@ void launch_interp(Plan* P, const Records& R, const double* xs, double* ys, int 
     if (R.n_in_work == 0) break;
     hipLaunchKernelGGL((interp_kernel<T, D>), dim3((unsigned)R.n_in_work), dim3(kThreads),
                        interp_smem<T>(P, a.gc, R.rs), P->stream, a,
-                       g.as<typename V2<T>::type>(), R.cell.as<int>(), R.pw.as<T>(), R.rs,
+                       gptr, R.cell.as<int>(), R.pw.as<T>(), R.rs,
                        R.in_work.as<int4>(), xs, ys);
     GP_CHECK_LAUNCH();
   }
@@ -1059,7 +1078,7 @@ void launch_spread_sub(Plan* P, const Records& R, const double* xs, int st) {
   hipLaunchKernelGGL((spread_sub_kernel<T, D, GCV>), dim3((unsigned)(P->n_bins * nsub)),        \
                      dim3(kSubThreads), smem, P->stream, a, st, xs, R.cell.as<int>(),           \
                      R.pw.as<T>(), R.rs, R.bin_start.as<int>(),                                 \
-                     P->gridA.as<typename V2<T>::type>())
+                     cur_gridA<typename V2<T>::type>(P))
     GP_GC_SWITCH(a.gc, GP_LAUNCH_SUB)
 #undef GP_LAUNCH_SUB
     GP_CHECK_LAUNCH();
@@ -1095,9 +1114,8 @@ void launch_interp_gather(Plan* P, const Records& R, const double* xs, double* y
   PhaseScope ps(P, PH_INTERP);
   NuArgs a = nu_args(P, R);
   a.add_noise = add_noise;
-  const DevBuf& g = P->fourstep ? P->gridC : P->gridA;
   hipLaunchKernelGGL((interp_gather_kernel<T, D, WT>), dim3((unsigned)((R.n + kThreads - 1) / kThreads)),
-                     dim3(kThreads), 0, P->stream, a, g.as<typename V2<T>::type>(), R.cell.as<int>(),
+                     dim3(kThreads), 0, P->stream, a, cur_interp_grid<typename V2<T>::type>(P), R.cell.as<int>(),
                      R.pw.as<T>(), R.rs, xs, ys);
   GP_CHECK_LAUNCH();
 }
@@ -1107,7 +1125,7 @@ size_t interp_super_smem(const Plan* P, int rs) {
   const size_t pc0 = (size_t)(2 * P->tile[0] + P->w - 1), pc1 = (size_t)(2 * P->tile[1] + P->w - 1);
   const size_t pc2 = P->d > 2 ? (size_t)(P->tile[2] + P->w - 1) : 1;
   return (pc0 | 1) * pc1 * pc2 * sizeof(typename V2<T>::type) +
-         (size_t)kPB2 * lds_stride(rs) * sizeof(T) + (P->d + 1) * kPB2 * sizeof(int) + 16;
+         (size_t)(P->d > 2 ? kPB2<3, T> : kPB2<2, T>) * (lds_stride(rs) * sizeof(T) + (P->d + 1) * sizeof(int)) + 16;
 }
 
 template <typename T>
@@ -1125,7 +1143,7 @@ void launch_interp_super(Plan* P, const Records& R, const double* xs, double* ys
   if (interp_super_smem<T>(P, R.rs) > kSmemCap) allow_big_lds(kern);
   hipLaunchKernelGGL(kern, dim3((unsigned)R.n_in_work2), dim3(kThreads),
                      interp_super_smem<T>(P, R.rs), P->stream, a,
-                     P->gridA.as<typename V2<T>::type>(), R.cell.as<int>(), R.pw.as<T>(), R.rs,
+                     cur_gridA<typename V2<T>::type>(P), R.cell.as<int>(), R.pw.as<T>(), R.rs,
                      R.bin_start.as<int>(), R.in_work2.as<int4>(), xs, ys);
   GP_CHECK_LAUNCH();
 }
@@ -1155,14 +1173,16 @@ void interp_dispatch(Plan* P, const Records& R, const double* xs, double* ys, in
 // Inverse (sign +1): truncated modes -> active box.
 void fft_all(Plan* P, int sign) {
   const int fp64 = P->precision == GP_FP64;
-  const int64_t G = P->npair, mc = P->mcount;
+  // every set of the current grid view: the sets are consecutive, so they
+  // transform as one batch of nsets * npair pairs
+  const int64_t G = (int64_t)P->npair * P->gv.nsets, mc = P->mcount;
   const int d = P->d;
   const int nf = P->nf[0];
   hipStream_t s = P->stream;
-  void* A = P->gridA.p;
-  void* B = P->gridB.p;
-  void* B2 = P->gridB2.p;
-  void* C = P->gridC.p;
+  void* A = P->gv.A;
+  void* B = P->gv.B;
+  void* B2 = P->gv.B2;
+  void* C = P->gv.C;
   FftPass q;
   q.sign = sign;
   // phase of a pass over dimension r
@@ -1265,6 +1285,61 @@ void matvec_sorted(Plan* P, const double* xs, double* ys, int add_noise) {
     forward_and_mix<float>(P, P->rec, xs);
     interp_dispatch<float>(P, P->rec, xs, ys, add_noise);
   }
+}
+
+int multi_capacity(Plan* P, int want) {
+  if (want <= P->m_cap) return want;
+  const size_t cs = P->precision == GP_FP64 ? 16 : 8;
+  const size_t per = (size_t)P->npair *
+                     (P->grid_elems[0] + P->grid_elems[1] + P->grid_elems[2] + P->grid_elems[3]) * cs;
+  size_t free_b = 0, total_b = 0;
+  GP_HIP(hipMemGetInfo(&free_b, &total_b));
+  const size_t fit = per > 0 ? (free_b / 2) / per : (size_t)want;
+  return (int)std::max<size_t>(1, std::min<size_t>((size_t)want, fit));
+}
+
+static void ensure_multi(Plan* P, int m) {
+  if (m <= P->m_cap) return;
+  const size_t cs = P->precision == GP_FP64 ? 16 : 8;
+  const size_t G = (size_t)P->npair * m;
+  P->mA.alloc(G * P->grid_elems[0] * cs);
+  P->mB.alloc(G * P->grid_elems[1] * cs);
+  if (P->grid_elems[2]) P->mB2.alloc(G * P->grid_elems[2] * cs);
+  P->mC.alloc(G * P->grid_elems[3] * cs);
+  // the 1-D four-step keeps zeros in A outside the active box (see fft_all)
+  if (P->fourstep) GP_HIP(hipMemsetAsync(P->mA.p, 0, P->mA.bytes, P->stream));
+  P->m_cap = m;
+}
+
+void matvec_multi_sorted(Plan* P, int m, const double* xs, double* ys, int add_noise) {
+  if (m < 1) return;
+  ensure_multi(P, m);
+  const Plan::GridView own = P->gv;
+  P->gv.A = P->mA.p;
+  P->gv.B = P->mB.p;
+  P->gv.B2 = P->mB2.p;
+  P->gv.C = P->mC.p;
+  P->gv.nsets = m;
+  try {
+    const int64_t n = P->n;
+    for (int j = 0; j < m; ++j) {
+      P->gv.cur = j;
+      if (P->precision == GP_FP64) spread_dispatch<double>(P, P->rec, xs + j * n);
+      else spread_dispatch<float>(P, P->rec, xs + j * n);
+    }
+    fft_all(P, -1);
+    mix_modes(P);
+    fft_all(P, +1);
+    for (int j = 0; j < m; ++j) {
+      P->gv.cur = j;
+      if (P->precision == GP_FP64) interp_dispatch<double>(P, P->rec, xs + j * n, ys + j * n, add_noise);
+      else interp_dispatch<float>(P, P->rec, xs + j * n, ys + j * n, add_noise);
+    }
+  } catch (...) {
+    P->gv = own;
+    throw;
+  }
+  P->gv = own;
 }
 
 void posterior_sorted(Plan* P, const double* xs, int64_t m, const double* tpts,

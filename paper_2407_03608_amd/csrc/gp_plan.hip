@@ -1166,6 +1166,16 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
   if (szB2) P->gridB2.alloc((size_t)G * szB2 * cs);
   P->gridC.alloc((size_t)G * szC * cs);
   if (P->fourstep) GP_HIP(hipMemsetAsync(P->gridA.p, 0, P->gridA.bytes, s));
+  P->grid_elems[0] = szA;
+  P->grid_elems[1] = szB;
+  P->grid_elems[2] = szB2;
+  P->grid_elems[3] = szC;
+  P->gv.A = P->gridA.p;
+  P->gv.B = P->gridB.p;
+  P->gv.B2 = P->gridB2.p;
+  P->gv.C = P->gridC.p;
+  P->gv.nsets = 1;
+  P->gv.cur = 0;
   P->vec.alloc((size_t)n * 8 * sizeof(double));
   P->cg_part.alloc(kCgBlocks * sizeof(double));
   P->cg_S.alloc(kCgScalars * sizeof(double));

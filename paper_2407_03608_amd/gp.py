@@ -118,6 +118,7 @@ EXPORTS = [
     "gp_cg_solve",
     "gp_cg_solve_refined",
     "gp_cg_solve_noalloc",
+    "gp_cg_solve_multi",
     "gp_posterior_mean",
     "gp_plan_set_stream",
     "gp_plan_destroy",
@@ -219,6 +220,9 @@ def load(path: str = LIB_PATH):
     L.gp_matvec.restype = _c_i
     L.gp_cg_solve.argtypes = [_c_p, _c_p, _c_p, _c_i, _c_d, _c_i, _c_i, ctypes.POINTER(GpCgInfo)]
     L.gp_cg_solve.restype = _c_i
+    L.gp_cg_solve_multi.argtypes = [_c_p, _c_i, _c_p, _c_p, _c_d, _c_i, _c_i, _c_p, _c_p,
+                                    ctypes.POINTER(GpCgInfo)]
+    L.gp_cg_solve_multi.restype = _c_i
     L.gp_cg_solve_noalloc.argtypes = [_c_p, _c_p, _c_p, _c_i, _c_d, _c_i, _c_i, ctypes.POINTER(GpCgInfo)]
     L.gp_cg_solve_noalloc.restype = _c_i
     L.gp_cg_solve_refined.argtypes = [_c_p, _c_p, _c_p, _c_p, _c_d, _c_d, _c_i, _c_i, _c_i,
@@ -351,6 +355,25 @@ class Plan:
         if rc not in (GP_OK, GP_ENOCONV):
             _check(rc)
         return alpha, _info_dict(info)
+
+    def cg_solve_multi(self, Y: torch.Tensor, tol: float = 1e-6, max_iter: int = 10000,
+                       block: bool = False):
+        """gp_cg_solve_multi: Y is (m, n) (row j = right-hand side j); block
+        selects block CG; returns (alpha (m, n), per-column iterations,
+        per-column relative residuals, info)."""
+        Y = _dev(Y, "Y")
+        if Y.dim() == 1:
+            Y = Y[None, :].contiguous()
+        m = Y.shape[0]
+        alpha = torch.zeros_like(Y)
+        its = (ctypes.c_int * m)()
+        rel = (ctypes.c_double * m)()
+        info = GpCgInfo()
+        rc = load().gp_cg_solve_multi(self._h, m, Y.data_ptr(), alpha.data_ptr(), float(tol),
+                                      int(max_iter), int(block), its, rel, ctypes.byref(info))
+        if rc not in (GP_OK, GP_ENOCONV):
+            _check(rc)
+        return alpha, list(its), list(rel), _info_dict(info)
 
     def cg_solve_noalloc(self, y: torch.Tensor, alpha: torch.Tensor, tol: float = 1e-6,
                          max_iter: int = 10000, use_x0: bool = False, replace_every: int = 0):

@@ -336,16 +336,81 @@ def test_posterior_mean(gp, d, prec, M):
     assert e < bar
 
 
+@pytest.mark.parametrize("d,n,M,prec", [(2, 600, 20, 0), (1, 300, 2600, 0), (3, 300, 8, 1), (2, 500, 20, 1)])
+def test_cg_solve_multi_matches_single_solves(gp, d, n, M, prec):
+    """gp_cg_solve_multi: m right-hand sides in lockstep, one operator
+    application for all of them per iteration (batched grids; one FFT batch;
+    one step-3 pass).  Every column equals gp_cg_solve on that column alone,
+    bit for bit, iteration count included; a zero column takes no iterations.
+    Cases: 2-D, the 1-D four-step grid, 3-D fp32."""
+    import torch
+    lmin, lmax = (0.01, 0.03) if M > 1000 else (0.08, 0.2)
+    prob = inputs.random_small(d, n, seed=90 + d, nu=1.5, lmin=lmin, lmax=lmax, eta=0.2)
+    tol_plan = 1e-9 if prec == 0 else 1e-4
+    P = _plan(gp, prob, tol=tol_plan, precision=prec, M=M)
+    rng = np.random.default_rng(3)
+    m = 5
+    Y = rng.standard_normal((m, prob.n))
+    Y[2] = 0.0
+    Y[3] = prob.y
+    tol = 1e-8 if prec == 0 else 1e-2  # the fp32 operator's CG stalls near 1e-3
+    A, its, rels, info = P.cg_solve_multi(cuda(Y), tol=tol, max_iter=3000)
+    say(f"case multi-rhs d={d} n={n} prec={prec}: iterations {its}, worst rel {info['rel_res']:.2e}")
+    assert info["status"] == 0 and its[2] == 0
+    Ah = host(A)
+    assert np.all(Ah[2] == 0.0)
+    for j in range(m):
+        a1, i1 = P.cg_solve(cuda(Y[j]), tol=tol, max_iter=3000)
+        assert i1["iters"] == its[j] and i1["rel_res"] == rels[j], (j, i1, its[j], rels[j])
+        assert np.array_equal(host(a1), Ah[j]), j
+    if prec == 0 and d == 2:
+        Kt = O.ktilde_entries(oracle_params(P.info()), prob.x, prob.sigma, prob.l)
+        ref = O.chol_solve(O.cholesky(Kt + prob.eta ** 2 * np.eye(prob.n)), prob.y)
+        A2, _, _, _ = P.cg_solve_multi(cuda(np.stack([prob.y, prob.y])), tol=1e-11, max_iter=5000)
+        assert rel(host(A2)[1], ref) <= 1e-6
+
+
+@pytest.mark.parametrize("d,n,M,m", [(2, 600, 20, 5), (1, 400, 120, 16), (2, 500, 20, 20), (3, 300, 8, 3)])
+def test_block_cg_vs_cholesky(gp, d, n, M, m):
+    """gp_cg_solve_multi with block = 1 (block CG, shared Krylov space, with
+    deflation): every column within 1e-6 of the oracle's Cholesky solution of
+    K~ + eta^2 I (eq:gprsolve), in fewer iterations than the separate solves;
+    m = 20 runs as blocks of 16 and 4; a zero column and a repeated column
+    (a rank-deficient block) are included."""
+    prob = inputs.random_small(d, n, seed=95 + d, nu=1.5, lmin=0.08, lmax=0.2, eta=0.2)
+    P = _plan(gp, prob, tol=1e-10, M=M)
+    rng = np.random.default_rng(4)
+    Y = rng.standard_normal((m, prob.n))
+    Y[0] = prob.y
+    if m > 2:
+        Y[1] = 0.0
+        Y[2] = Y[0]
+    A, its, rels, info = P.cg_solve_multi(cuda(Y), tol=1e-11, max_iter=5000, block=True)
+    Kt = O.ktilde_entries(oracle_params(P.info()), prob.x, prob.sigma, prob.l)
+    L = O.cholesky(Kt + prob.eta ** 2 * np.eye(prob.n))
+    Ah = host(A)
+    worst = max(rel(Ah[j], O.chol_solve(L, Y[j])) for j in range(m) if np.any(Y[j]))
+    _, i1 = P.cg_solve(cuda(Y[0]), tol=1e-11, max_iter=5000)
+    say(f"case block CG d={d} m={m}: {its[0]} block iterations (single solve {i1['iters']}), "
+        f"worst rel res {info['rel_res']:.2e}, worst error vs Cholesky {worst:.2e}")
+    assert info["status"] == 0 and max(rels) <= 1e-11
+    assert worst <= 1e-6
+    if m > 2:
+        assert np.all(Ah[1] == 0.0) and rel(Ah[2], Ah[0]) < 1e-9
+    assert its[0] <= i1["iters"]
+
+
 @pytest.mark.parametrize("d", [1, 2])
 def test_posterior_cov_vs_oracle(gp, d):
-    """eq:postcov: GPU covariance (one CG solve per target) against the oracle's
-    Schur complement of K~ entries (Cholesky), same plan parameters."""
+    """eq:postcov: GPU covariance (multi-right-hand-side CG over blocks of up
+    to 16 targets) against the oracle's Schur complement of K~ entries
+    (Cholesky), same plan parameters."""
     n = 200 if d == 1 else 120
     prob = inputs.random_small(d, n, seed=50 + d, nu=1.5, lmin=0.12, lmax=0.2, eta=0.3)
     P = _plan(gp, prob, tol=1e-6, nufft_tol=1e-11, M=60 if d == 1 else 14)
     info = P.info()
     rng = np.random.default_rng(5)
-    m = 6
+    m = 6 if d == 1 else 20  # d = 2: two blocks of the multi-right-hand-side solve (16 + 4)
     xt = rng.uniform(prob.x.min(0), prob.x.max(0), size=(m, d))
     lt = rng.uniform(prob.l.min(), prob.l.max(), size=m)
     st = rng.uniform(0.7, 1.3, size=m)
