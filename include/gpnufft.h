@@ -102,8 +102,17 @@ typedef struct {
                                chunk of grid pairs, (point, window row, pair) items */
   int step3;                /* step 3 of section 4.2 (rem:step3): 0 = precomputed tensor
                                A_k'k, stored once per distinct |n|^2 (default); 1 = direct
-                               sum over the t nodes at every mode */
+                               sum over the t nodes at every mode; 2 = the precomputed rows
+                               in low-rank form A ~ sum_a R_a R_a' (pivoted Cholesky of each
+                               row to tol/100 of its largest diagonal; the rank is revealed
+                               row by row) */
   void* stream;             /* hipStream_t; NULL = null stream */
+  int keep_t;               /* 0 (default): the leading t nodes whose Fourier multipliers
+                               G^_kj[n] are constant over the mode box to 1e-3 tol (the
+                               exponent 2 pi^2 sigma_max^2 chi_j^2 dw^2 d M^2 <= 1e-3 tol)
+                               are merged into one term before step 3 (their weights
+                               C_kj = (2 pi chi_j^2)^(d/2) sigma_k^d factor, so the merged
+                               term is exact up to that flatness); 1: keep every node */
 } gp_opts;
 
 /* What the plan chose (all in the mapped coordinates x' = (x - center) * scale). */
@@ -137,6 +146,9 @@ typedef struct {
                                GP_SPREAD_OWNER (gp_opts.spread resolved) */
   int interp;               /* interpolation variant in use (see gp_opts.interp) */
   int64_t a_rows;           /* rows of the precomputed A table (distinct |n|^2) */
+  int n_t_merged;           /* leading t nodes merged into one term (see gp_opts.keep_t) */
+  int lr_rank_max;          /* step3 = 2: largest rank of a row of A (0 otherwise) */
+  double lr_rank_mean;      /* step3 = 2: mean rank over the rows */
 } gp_plan_params;
 
 typedef struct {

@@ -230,6 +230,9 @@ static void fill_params(const Plan& P, gp_plan_params* o) {
   o->spread = P.spread_mode;
   o->interp = P.interp_mode;
   o->a_rows = P.a_rows;
+  o->n_t_merged = P.n_flat;
+  o->lr_rank_max = P.lr_rank_max;
+  o->lr_rank_mean = P.lr_rank_mean;
 }
 
 int gp_plan_info(gp_plan_t h, gp_plan_params* o) {

@@ -130,7 +130,9 @@ struct Plan {
   int L1 = 0, L2 = 0;
   int nk = 0;                 // real grids = N_sigma + 1
   int npair = 0;              // complex grids = ceil(nk/2)
-  int nt_eff = 0;             // t nodes (N_t + 1, or 1 for SE)
+  int nt_eff = 0;             // t nodes in the step-3 tables (N_t + 1 - n_flat + [n_flat > 0], or 1 for SE)
+  int n_flat = 0;             // leading t nodes merged into one constant term (0: none)
+  double tol = 0;             // the plan's accuracy target
   int64_t mcount = 0;         // (2M+1)
   // host copies of the tables (for info / tests)
   std::vector<double> sig_nodes, bary, vt, chi;
@@ -142,7 +144,10 @@ struct Plan {
   DevBuf gtab;                // T [nt][nk][M+1]: C_kj * exp(-tau_kj n^2) for dim 0
   DevBuf etab;                // T [nt][nk][M+1]: exp(-tau_kj n^2) for dims >= 1
   DevBuf vtd;                 // T [nt] v~_j
-  int step3 = 0;              // 0: radial precomputed A, 1: direct t-sum
+  int step3 = 0;              // 0: radial precomputed A, 1: direct t-sum, 2: low-rank radial A
+  DevBuf lr_off;              // int64 [a_rows + 1]: start of each row's factors in atab (step3 = 2)
+  int lr_rank_max = 0;        // largest rank over the rows (step3 = 2)
+  double lr_rank_mean = 0;
   int spread_mode = GP_SPREAD_OWNER;  // resolved gp_opts.spread (never GP_SPREAD_AUTO)
   int interp_mode = 0;        // 0 default, 1 cache gather, 2 per-bin LDS tiles
   int64_t a_rows = 0;         // distinct |n|^2 values (rows of A)

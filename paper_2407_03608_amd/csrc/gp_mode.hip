@@ -240,6 +240,112 @@ __global__ __launch_bounds__(kThreads) void mode_radial_kernel(
   }
 }
 
+// Step 3 with the rows of A in low-rank form (rem:step3, last paragraph):
+// A(|n|^2) ~ sum_a R_a R_a', rank_r = (off[r+1] - off[r]) / NK factors of NK
+// entries each.  a = R (R' b): 2 rank NK multiply-adds per complex value
+// instead of NK^2.  Orthant points and sign patterns as in mode_radial_kernel.
+template <typename T, int NK>
+__global__ __launch_bounds__(kThreads) void mode_lowrank_kernel(
+    RadialArgs a, typename V2<T>::type* __restrict__ C, const T* __restrict__ Rtab,
+    const int64_t* __restrict__ off, const int* __restrict__ rowidx, const T* __restrict__ dec) {
+  using V = typename V2<T>::type;
+  const int64_t tid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (tid >= a.Q) return;
+  const int64_t M1 = a.M + 1;
+  int64_t an[3] = {0, 0, 0};
+  {
+    int64_t q = tid;
+    for (int r = 0; r < a.d; ++r) {
+      an[r] = q % M1;
+      q /= M1;
+    }
+  }
+  const int64_t s2 = an[0] * an[0] + an[1] * an[1] + an[2] * an[2];
+  const int64_t row = a.d == 1 ? an[0] : (int64_t)rowidx[s2];
+  const T* Rr = Rtab + off[row];
+  const int rank = (int)((off[row + 1] - off[row]) / NK);
+  T D = T(1);
+  for (int r = 0; r < a.d; ++r) D *= dec[r * M1 + an[r]];
+  int first_nz = -1;
+  for (int r = 0; r < a.d; ++r)
+    if (an[r] != 0) {
+      first_nz = r;
+      break;
+    }
+  const int npat = 1 << (a.d - 1);
+  for (int set = 0; set < a.nsets; ++set)
+  for (int pg = 0; pg < npat; pg += 2) {
+    V* __restrict__ Cs = C + set * a.set_stride;
+    bool keep[2];
+    int64_t st0[2], st1[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int pat = pg + h;
+      keep[h] = pat < npat;
+      int64_t nv[3] = {0, 0, 0}, nvc[3] = {0, 0, 0};
+      for (int r = 0; r < a.d; ++r) {
+        const int neg = r == 0 ? 0 : ((pat >> (r - 1)) & 1);
+        if (neg && (an[r] == 0 || r == first_nz)) keep[h] = false;
+        nv[r] = neg ? -an[r] : an[r];
+        nvc[r] = -nv[r];
+      }
+      st0[h] = keep[h] ? radial_store(a, nv) : 0;
+      st1[h] = keep[h] ? radial_store(a, nvc) : 0;
+    }
+    if (!keep[0] && !keep[1]) continue;
+    V b[2][NK];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int g = 0; g < NK / 2; ++g) {
+        V z = V{T(0), T(0)}, zc = V{T(0), T(0)};
+        if (keep[h] && g < a.npair) {
+          z = Cs[g * a.pair_stride + st0[h]];
+          zc = Cs[g * a.pair_stride + st1[h]];
+        }
+        b[h][2 * g] = V{T(0.5) * (z.x + zc.x) * D, T(0.5) * (z.y - zc.y) * D};
+        b[h][2 * g + 1] = V{T(0.5) * (z.y + zc.y) * D, T(-0.5) * (z.x - zc.x) * D};
+      }
+    V acc[2][NK];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int k = 0; k < NK; ++k) acc[h][k] = V{T(0), T(0)};
+    for (int f = 0; f < rank; ++f) {
+      const T* ra = Rr + (int64_t)f * NK;
+      T rv[NK];
+#pragma unroll
+      for (int k = 0; k < NK; ++k) rv[k] = ra[k];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        V t = V{T(0), T(0)};
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+          t.x += rv[k] * b[h][k].x;
+          t.y += rv[k] * b[h][k].y;
+        }
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+          acc[h][k].x += rv[k] * t.x;
+          acc[h][k].y += rv[k] * t.y;
+        }
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (!keep[h]) continue;
+#pragma unroll
+      for (int g = 0; g < NK / 2; ++g) {
+        if (g >= a.npair) break;
+        const V pp = V{acc[h][2 * g].x * D, acc[h][2 * g].y * D};
+        const V qq = V{acc[h][2 * g + 1].x * D, acc[h][2 * g + 1].y * D};
+        Cs[g * a.pair_stride + st0[h]] = V{pp.x - qq.y, pp.y + qq.x};
+        if (st1[h] != st0[h]) Cs[g * a.pair_stride + st1[h]] = V{pp.x + qq.y, -pp.y + qq.x};
+      }
+    }
+  }
+}
+
 // d = 1: the M+1 orthant points are too few to fill the chip one per thread,
 // so each point takes a group of NK lanes: lane j forms b_j, computes row j
 // of A b (terms in the order k = 0..NK-1, as the per-thread kernel adds them),
@@ -354,6 +460,13 @@ void launch_radial_nk(Plan* P) {
   a.nsets = P->gv.nsets;
   a.set_stride = P->npair * a.pair_stride;
   auto* C = static_cast<typename V2<T>::type*>(P->gv.C);
+  if (P->step3 == 2) {
+    hipLaunchKernelGGL((mode_lowrank_kernel<T, NK>), dim3((unsigned)((a.Q + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, P->stream, a, C, P->atab.as<T>(), P->lr_off.as<int64_t>(),
+                       P->d > 1 ? P->rowidx.as<int>() : nullptr, P->dec.as<T>());
+    GP_CHECK_LAUNCH();
+    return;
+  }
   if (P->d == 1) {
     constexpr int PPB = kThreads / NK;
     for (int set = 0; set < a.nsets; ++set) {
@@ -373,7 +486,7 @@ void launch_radial_nk(Plan* P) {
 template <typename T>
 void launch_mode(Plan* P) {
   const int nk2 = 2 * P->npair;
-  if (P->step3 == 0) {
+  if (P->step3 != 1) {
     switch (nk2) {
 #define GP_R(N) case N: launch_radial_nk<T, N>(P); return;
       GP_R(2) GP_R(4) GP_R(6) GP_R(8) GP_R(10) GP_R(12) GP_R(14) GP_R(16) GP_R(18) GP_R(20)

@@ -13,6 +13,7 @@
 #include <map>
 #include <cstring>
 #include <limits>
+#include <thread>
 
 #include "gp_internal.h"
 
@@ -733,7 +734,6 @@ void choose_params(Plan* P, int d, double nu, double tol, double lmin, double lm
   } else {
     t_grid_rule(nu, eps, &P->t_min, &P->t_max, &P->n_t);
   }
-  P->nt_eff = P->se ? 1 : P->n_t + 1;
 
   // ---- Fourier grid spacing: aliasing images at distance >= 1/dw - 2 see the
   // kernel's own tail; ask phi_nu(r) <= eps/10 there for the widest length.
@@ -767,6 +767,28 @@ void choose_params(Plan* P, int d, double nu, double tol, double lmin, double lm
   }
   P->pred_tail = spectral_tail(nu, d, lpmin, P->M * P->dw);
   P->mcount = 2 * P->M + 1;
+
+  // ---- flat t nodes (rem:step3): G^_kj[n] = C_kj exp(-tau_kj |n|^2) with
+  // tau_kj = 2 pi^2 sigma_k^2 chi_j^2 dw^2; where even the largest exponent
+  // over the mode box, tau at sigma_max times d M^2, is <= 1e-3 tol, the term
+  // is constant over the box to that accuracy.  chi_j grows with j, so these
+  // are the leading nodes; two or more of them are merged into one term.
+  P->tol = tol;
+  P->n_flat = 0;
+  if (!P->se && !opts.keep_t) {
+    const double dt = (P->t_max - P->t_min) / P->n_t;
+    const double smax2 = P->s_max * P->s_max;
+    int nf0 = 0;
+    for (int j = 0; j <= P->n_t; ++j) {
+      const double t = P->t_min + j * dt;
+      const double chi2 = std::exp(t) / nu;
+      const double x = 2 * PI * PI * smax2 * chi2 * P->dw * P->dw * (double)d * (double)P->M * (double)P->M;
+      if (!(x <= 1e-3 * tol)) break;
+      ++nf0;
+    }
+    P->n_flat = nf0 >= 2 ? nf0 : 0;
+  }
+  P->nt_eff = P->se ? 1 : P->n_t + 1 - P->n_flat + (P->n_flat > 0 ? 1 : 0);
 
   // ---- spreading window (exponential of semicircle) and oversampled grid
   double ntol = opts.nufft_tol > 0 ? opts.nufft_tol : eps;
@@ -871,6 +893,79 @@ void choose_params(Plan* P, int d, double nu, double tol, double lmin, double lm
   for (int r = 0; r < d; ++r) P->nsrc = std::max(P->nsrc, (P->w - 2) / P->tile[r] + 2);
 }
 
+// Low-rank factors of the step-3 rows (rem:step3, last paragraph): row r of A
+// (nk x nk, symmetric positive semidefinite, stored as the upper triangle of
+// width nkp) is factored by pivoted Cholesky, A ~ sum_a R_a R_a', taking
+// pivots while the largest remaining diagonal exceeds rel times the row's
+// largest diagonal; the rank so revealed varies by row.  Output: rows[off[r]
+// .. off[r+1]) holds rank_r vectors of nkp entries (R_a[k], zero for k >= nk).
+// Rows are independent and are factored by several host threads.
+void lowrank_rows(int64_t nrows, int nk, int nkp, const std::vector<double>& A, double rel,
+                  std::vector<int64_t>& off, std::vector<double>& rows, int* rank_max,
+                  double* rank_mean) {
+  const int npk = nkp * (nkp + 1) / 2;
+  std::vector<int> rank(nrows);
+  std::vector<double> fac((size_t)nrows * nk * nkp);  // up to nk factors per row
+  auto work = [&](int64_t r0, int64_t r1) {
+    std::vector<double> S((size_t)nk * nk), L((size_t)nk * nk);
+    std::vector<int> perm(nk);
+    for (int64_t r = r0; r < r1; ++r) {
+      const double* a = A.data() + (size_t)r * npk;
+      for (int k1 = 0, p = 0; k1 < nkp; ++k1)
+        for (int k2 = k1; k2 < nkp; ++k2, ++p)
+          if (k1 < nk && k2 < nk) S[(size_t)k1 * nk + k2] = S[(size_t)k2 * nk + k1] = a[p];
+      double dmax = 0.0;
+      for (int k = 0; k < nk; ++k) {
+        perm[k] = k;
+        dmax = std::max(dmax, S[(size_t)k * nk + k]);
+      }
+      std::fill(L.begin(), L.end(), 0.0);  // L[k][a]: factor a at width k (original order)
+      int rk = 0;
+      for (int a = 0; a < nk; ++a) {
+        int best = a;
+        for (int i = a + 1; i < nk; ++i)
+          if (S[(size_t)perm[i] * nk + perm[i]] > S[(size_t)perm[best] * nk + perm[best]]) best = i;
+        std::swap(perm[a], perm[best]);
+        const int pa = perm[a];
+        const double dd = S[(size_t)pa * nk + pa];
+        if (!(dmax > 0.0) || !(dd > rel * dmax)) break;
+        const double lv = std::sqrt(dd);
+        for (int i = a; i < nk; ++i) L[(size_t)perm[i] * nk + a] = S[(size_t)perm[i] * nk + pa] / lv;
+        for (int i = a + 1; i < nk; ++i)
+          for (int q = a + 1; q < nk; ++q)
+            S[(size_t)perm[i] * nk + perm[q]] -= L[(size_t)perm[i] * nk + a] * L[(size_t)perm[q] * nk + a];
+        ++rk;
+      }
+      rank[r] = rk;
+      double* f = fac.data() + (size_t)r * nk * nkp;
+      for (int a = 0; a < rk; ++a)
+        for (int k = 0; k < nkp; ++k) f[(size_t)a * nkp + k] = k < nk ? L[(size_t)k * nk + a] : 0.0;
+    }
+  };
+  const int nth = (int)std::max<unsigned>(1, std::min<unsigned>(16, std::thread::hardware_concurrency()));
+  std::vector<std::thread> th;
+  const int64_t chunk = (nrows + nth - 1) / nth;
+  for (int t = 0; t < nth; ++t) {
+    const int64_t r0 = t * chunk, r1 = std::min<int64_t>(nrows, r0 + chunk);
+    if (r0 < r1) th.emplace_back(work, r0, r1);
+  }
+  for (auto& t : th) t.join();
+  off.assign(nrows + 1, 0);
+  int64_t sum = 0;
+  int mx = 0;
+  for (int64_t r = 0; r < nrows; ++r) {
+    off[r + 1] = off[r] + (int64_t)rank[r] * nkp;
+    sum += rank[r];
+    mx = std::max(mx, rank[r]);
+  }
+  rows.resize((size_t)off[nrows]);
+  for (int64_t r = 0; r < nrows; ++r)
+    std::copy(fac.begin() + (size_t)r * nk * nkp, fac.begin() + (size_t)r * nk * nkp + (off[r + 1] - off[r]),
+              rows.begin() + off[r]);
+  *rank_max = mx;
+  *rank_mean = nrows > 0 ? (double)sum / nrows : 0.0;
+}
+
 int build_plan(int d, int64_t n, const double* pts, const double* sigma, const double* l,
                double nu, double eta, double tol, const gp_opts* opts_in, Plan* P,
                bool query_only, size_t* bytes_out) {
@@ -952,7 +1047,8 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
   P->npair = (P->nk + 1) / 2;
 
   // ---- step 3 variant; radial rows of the precomputed tensor
-  P->step3 = opts.step3 ? 1 : 0;
+  if (opts.step3 < 0 || opts.step3 > 2) throw Error{GP_EINVAL, "opts.step3 must be 0, 1 or 2"};
+  P->step3 = opts.step3;
   if (opts.spread < 0 || opts.spread > 2) throw Error{GP_EINVAL, "opts.spread must be 0, 1 or 2"};
   P->spread_mode = opts.spread != GP_SPREAD_AUTO ? opts.spread : GP_SPREAD_OWNER;
   if (opts.interp < 0 || opts.interp > 2) throw Error{GP_EINVAL, "opts.interp must be 0, 1 or 2"};
@@ -960,7 +1056,7 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
   P->nkp = P->nk + (P->nk & 1);
   std::vector<double> svals;
   std::vector<int> rowmap;
-  if (P->step3 == 0) {
+  if (P->step3 != 1) {
     const int64_t M = P->M;
     if (d == 1) {
       svals.resize(M + 1);
@@ -1011,8 +1107,9 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
   bytes += (size_t)n * (sizeof(int) * (1 + d) + ts * (d * P->w + P->nk + 1));
   bytes += (size_t)(P->n_bins + 1) * sizeof(int);
   bytes += work_list_bound_bytes(P, n, cs);
-  if (P->step3 == 0)
-    bytes += (size_t)P->a_rows * (P->nkp * (P->nkp + 1) / 2) * ts + rowmap.size() * sizeof(int);
+  if (P->step3 != 1)  // the low-rank rows (step3 = 2) hold at most the full row's size
+    bytes += (size_t)P->a_rows * (P->nkp * (P->nkp + 1) / 2) * ts + rowmap.size() * sizeof(int) +
+             (P->step3 == 2 ? (size_t)(P->a_rows + 1) * sizeof(int64_t) : 0);
   else
     bytes += (size_t)P->nt_eff * P->nk * (P->M + 1) * ts * 2;
   bytes += (size_t)n * 8 * sizeof(double) + (kCgBlocks + kCgScalars) * sizeof(double);  // vectors
@@ -1035,8 +1132,9 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
       P->bary[k] = ((k % 2) ? -1.0 : 1.0) * ((k == 0 || k == P->n_sigma) ? 0.5 : 1.0);
     }
   }
-  P->vt.resize(P->nt_eff);
-  P->chi.resize(P->nt_eff);
+  const int nt_paper = P->se ? 1 : P->n_t + 1;
+  P->vt.resize(nt_paper);
+  P->chi.resize(nt_paper);
   const double dwd = std::pow(P->dw, d);
   if (P->se) {
     P->vt[0] = dwd;
@@ -1052,17 +1150,45 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
       P->chi[j] = ch;
     }
   }
+  // The step-3 terms: per table node j and width k, the weight v~_j, the
+  // constant C_kj and the exponent tau_kj of G^_kj[n] = C_kj exp(-tau_kj |n|^2).
+  // The merged flat nodes form one term with tau = 0: their C_kj =
+  // (2 pi chi_j^2)^(d/2) sigma_k^d, so sum_j v~_j C_k'j C_kj over them is
+  // W sigma_k'^d sigma_k^d with W = sum_j v~_j (2 pi chi_j^2)^d.
+  std::vector<double> tvt(P->nt_eff), tcst((size_t)P->nt_eff * P->nk), ttau((size_t)P->nt_eff * P->nk);
+  {
+    int jt = 0;
+    if (P->n_flat > 0) {
+      double W = 0.0;
+      for (int j = 0; j < P->n_flat; ++j) W += P->vt[j] * std::pow(2 * PI * P->chi[j] * P->chi[j], (double)d);
+      tvt[0] = W;
+      for (int k = 0; k < P->nk; ++k) {
+        tcst[k] = std::pow(P->sig_nodes[k], (double)d);
+        ttau[k] = 0.0;
+      }
+      jt = 1;
+    }
+    for (int j = P->n_flat; j < nt_paper; ++j, ++jt) {
+      tvt[jt] = P->vt[j];
+      for (int k = 0; k < P->nk; ++k) {
+        const double s2 = P->sig_nodes[k] * P->sig_nodes[k] * P->chi[j] * P->chi[j];
+        tcst[(size_t)jt * P->nk + k] = std::pow(2 * PI * s2, 0.5 * d);
+        ttau[(size_t)jt * P->nk + k] = 2 * PI * PI * s2 * P->dw * P->dw;
+      }
+    }
+    if (jt != P->nt_eff) throw Error{GP_EDEVICE, "internal: t node count"};
+  }
 
   // Fourier multipliers of G_{k,t_j} (eq:Gkt) on the grid, separated by
-  // dimension: G^_{kj}[n] = (2 pi s^2)^(d/2) prod_r exp(-2 pi^2 s^2 dw^2 n_r^2),
-  // s = sigma_k chi_j.  gtab carries the constant and dimension 0, etab the rest.
+  // dimension: G^_{kj}[n] = C_kj prod_r exp(-tau_kj n_r^2), C_kj = (2 pi s^2)^(d/2),
+  // tau_kj = 2 pi^2 s^2 dw^2, s = sigma_k chi_j.  gtab carries the constant and
+  // dimension 0, etab the rest.
   const int64_t M1 = P->M + 1;
   std::vector<double> g0((size_t)P->nt_eff * P->nk * M1), e1((size_t)P->nt_eff * P->nk * M1);
   for (int j = 0; j < P->nt_eff; ++j)
     for (int k = 0; k < P->nk; ++k) {
-      double s2 = P->sig_nodes[k] * P->sig_nodes[k] * P->chi[j] * P->chi[j];
-      double cst = std::pow(2 * PI * s2, 0.5 * d);
-      double tau = 2 * PI * PI * s2 * P->dw * P->dw;
+      const double cst = tcst[(size_t)j * P->nk + k];
+      const double tau = ttau[(size_t)j * P->nk + k];
       for (int64_t m = 0; m < M1; ++m) {
         double e = std::exp(-tau * (double)m * (double)m);
         g0[((size_t)j * P->nk + k) * M1 + m] = cst * e;
@@ -1094,13 +1220,8 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
     upload(P->etab, e1);
   } else {
     // precomputed tensor, one row per distinct |n|^2
-    std::vector<double> tau((size_t)P->nt_eff * P->nk), cst((size_t)P->nt_eff * P->nk);
-    for (int j = 0; j < P->nt_eff; ++j)
-      for (int k = 0; k < P->nk; ++k) {
-        double s2 = P->sig_nodes[k] * P->sig_nodes[k] * P->chi[j] * P->chi[j];
-        cst[j * P->nk + k] = std::pow(2 * PI * s2, 0.5 * d);
-        tau[j * P->nk + k] = 2 * PI * PI * s2 * P->dw * P->dw;
-      }
+    const std::vector<double>& tau = ttau;
+    const std::vector<double>& cst = tcst;
     DevBuf dsv, dtau, dcst, dvt;
     auto up64 = [&](DevBuf& b, const std::vector<double>& v) {
       b.alloc(v.size() * sizeof(double));
@@ -1109,20 +1230,42 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
     up64(dsv, svals);
     up64(dtau, tau);
     up64(dcst, cst);
-    up64(dvt, P->vt);
+    up64(dvt, tvt);
     const int npk = P->nkp * (P->nkp + 1) / 2;
     const int64_t tot = P->a_rows * npk;
-    P->atab.alloc((size_t)tot * ts);
     const unsigned nb = (unsigned)((tot + 255) / 256);
-    if (P->precision == GP_FP64)
+    if (P->step3 == 0) {
+      P->atab.alloc((size_t)tot * ts);
+      if (P->precision == GP_FP64)
+        hipLaunchKernelGGL(atab_kernel<double>, dim3(nb), dim3(256), 0, s, P->a_rows, npk, P->nkp,
+                           P->nk, P->nt_eff, dsv.as<double>(), dtau.as<double>(), dcst.as<double>(),
+                           dvt.as<double>(), P->atab.as<double>());
+      else
+        hipLaunchKernelGGL(atab_kernel<float>, dim3(nb), dim3(256), 0, s, P->a_rows, npk, P->nkp,
+                           P->nk, P->nt_eff, dsv.as<double>(), dtau.as<double>(), dcst.as<double>(),
+                           dvt.as<double>(), P->atab.as<float>());
+      GP_CHECK_LAUNCH();
+    } else {
+      // low-rank form of rem:step3 (last paragraph): the fp64 rows, factored
+      // on the host row by row as A ~ R' R by pivoted Cholesky, keeping the
+      // factors whose pivots exceed tol/100 of the row's largest diagonal
+      DevBuf full;
+      full.alloc((size_t)tot * sizeof(double));
       hipLaunchKernelGGL(atab_kernel<double>, dim3(nb), dim3(256), 0, s, P->a_rows, npk, P->nkp,
                          P->nk, P->nt_eff, dsv.as<double>(), dtau.as<double>(), dcst.as<double>(),
-                         dvt.as<double>(), P->atab.as<double>());
-    else
-      hipLaunchKernelGGL(atab_kernel<float>, dim3(nb), dim3(256), 0, s, P->a_rows, npk, P->nkp,
-                         P->nk, P->nt_eff, dsv.as<double>(), dtau.as<double>(), dcst.as<double>(),
-                         dvt.as<double>(), P->atab.as<float>());
-    GP_CHECK_LAUNCH();
+                         dvt.as<double>(), full.as<double>());
+      GP_CHECK_LAUNCH();
+      std::vector<double> hA((size_t)tot);
+      GP_HIP(hipMemcpyAsync(hA.data(), full.p, hA.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+      GP_HIP(hipStreamSynchronize(s));
+      std::vector<int64_t> off;
+      std::vector<double> rows;
+      lowrank_rows(P->a_rows, P->nk, P->nkp, hA, 1e-2 * tol, off, rows, &P->lr_rank_max,
+                   &P->lr_rank_mean);
+      P->lr_off.alloc(off.size() * sizeof(int64_t));
+      GP_HIP(hipMemcpyAsync(P->lr_off.p, off.data(), off.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+      upload(P->atab, rows);
+    }
     if (d > 1) {
       P->rowidx.alloc(rowmap.size() * sizeof(int));
       GP_HIP(hipMemcpyAsync(P->rowidx.p, rowmap.data(), rowmap.size() * sizeof(int),
@@ -1130,7 +1273,7 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
     }
     GP_HIP(hipStreamSynchronize(s));
   }
-  upload(P->vtd, P->vt);
+  upload(P->vtd, tvt);
   upload(P->dec, dec);
   P->nodes_d.alloc(P->nk * sizeof(double));
   P->bary_d.alloc(P->nk * sizeof(double));

@@ -59,6 +59,7 @@ class GpOpts(ctypes.Structure):
         ("interp", _c_i),
         ("step3", _c_i),
         ("stream", _c_p),
+        ("keep_t", _c_i),
     ]
 
 
@@ -95,6 +96,9 @@ class GpPlanParams(ctypes.Structure):
         ("spread", _c_i),
         ("interp", _c_i),
         ("a_rows", _c_i64),
+        ("n_t_merged", _c_i),
+        ("lr_rank_max", _c_i),
+        ("lr_rank_mean", _c_d),
     ]
 
 

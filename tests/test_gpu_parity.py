@@ -66,16 +66,36 @@ def test_matvec_fp64_vs_oracle(gp, d, n, M, nu):
 
 @pytest.mark.parametrize("d,M,prec", [(1, 150, 0), (2, 24, 0), (3, 8, 0), (2, 24, 1), (1, 2600, 0)])
 def test_step3_variants_agree(gp, d, M, prec):
-    """rem:step3: the precomputed tensor (one row per |n|^2) and the direct t-sum
-    give the same operator, and both match the oracle."""
+    """rem:step3: the precomputed tensor (one row per |n|^2), the direct t-sum
+    and the precomputed rows in low-rank form (pivoted Cholesky to tol/100 of
+    each row) give the same operator, and each matches the oracle."""
     lmin, lmax = (0.01, 0.03) if M > 1000 else (0.08, 0.2)
     prob = inputs.random_small(d, 300, seed=50 + d, nu=1.5, lmin=lmin, lmax=lmax)
     tol = 1e-9 if prec == 0 else 1e-4
     bar = FP64_TOL if prec == 0 else FP32_TOL
     Pr, info_r, a, got_r, ref = _check_matvec(gp, prob, tol=tol, precision=prec, bar=bar, M=M, step3=0)
     Pd, info_d, _, got_d, _ = _check_matvec(gp, prob, tol=tol, precision=prec, bar=bar, M=M, step3=1)
-    assert info_r["step3"] == 0 and info_d["step3"] == 1 and info_r["a_rows"] > 0
+    Pl, info_l, _, got_l, _ = _check_matvec(gp, prob, tol=tol, precision=prec, bar=bar, M=M, step3=2)
+    say(f"  low-rank rows: rank max {info_l['lr_rank_max']} mean {info_l['lr_rank_mean']:.2f} "
+        f"of {2 * info_l['n_pairs']}")
+    assert info_r["step3"] == 0 and info_d["step3"] == 1 and info_l["step3"] == 2 and info_r["a_rows"] > 0
+    assert 1 <= info_l["lr_rank_max"] <= 2 * info_l["n_pairs"]
     assert rel(got_r, got_d) < (1e-11 if prec == 0 else 1e-5)
+    assert rel(got_l, got_r) < (1e-9 if prec == 0 else 1e-5)
+
+
+@pytest.mark.parametrize("step3", [0, 1])
+def test_merged_flat_t_terms(gp, step3):
+    """The leading t nodes whose multipliers are flat over the mode box (to
+    1e-3 tol) are merged into one term: the operator with and without the merge
+    agrees to ~1e-3 tol and both meet the bar against the oracle, whose K~ keeps
+    every node (nu = 1/2 at tol 1e-8 has dozens of such nodes)."""
+    prob = inputs.random_small(2, 500, seed=77, nu=0.5, lmin=0.05, lmax=0.1)
+    Pm, im, a, got_m, ref = _check_matvec(gp, prob, tol=1e-8, M=40, step3=step3)
+    Pk, ik, _, got_k, _ = _check_matvec(gp, prob, tol=1e-8, M=40, step3=step3, keep_t=1)
+    say(f"  merged {im['n_t_merged']} of {im['n_t'] + 1} t nodes; merged vs kept {rel(got_m, got_k):.2e}")
+    assert im["n_t_merged"] >= 2 and ik["n_t_merged"] == 0
+    assert rel(got_m, got_k) <= 1e-9
 
 
 @pytest.mark.parametrize("d,M,prec", [(1, 150, 0), (2, 24, 0), (3, 8, 0), (2, 24, 1), (3, 8, 1)])

@@ -269,3 +269,26 @@ def test_rules_reject_bad_arguments(args, code):
     with pytest.raises(gp.GpError) as e:
         gp.plan_rules(*args)
     assert e.value.code == code
+
+
+@pytest.mark.parametrize("d,nu,tol,lmin,lmax,M", [(2, 0.5, 1e-8, 0.02, 0.04, 0), (2, 0.5, 1e-8, 0.02, 0.04, 40),
+                                                (1, 0.5, 1e-10, 0.05, 0.1, 200), (2, 1.5, 1e-8, 0.05, 0.1, 0)])
+def test_flat_t_nodes_merged_where_constant_over_the_box(d, nu, tol, lmin, lmax, M):
+    """rem:step3 with the reading that t terms whose Fourier multiplier is
+    constant over the mode box merge into one term: the merged nodes are exactly
+    the leading nodes whose largest exponent 2 pi^2 sigma_max^2 chi_j^2 dw^2 d M^2
+    is <= 1e-3 tol (recomputed here from the plan's t grid), and keep_t = 1
+    turns the merge off."""
+    kw = {"M": M} if M else {}
+    r = gp.plan_rules(d, nu, tol, lmin, lmax, 1.0, **kw)
+    nt = r["n_t"]
+    t = r["t_min"] + np.arange(nt + 1) / nt * (r["t_max"] - r["t_min"])
+    chi2 = np.exp(t) / nu
+    x = 2 * np.pi ** 2 * r["s_max"] ** 2 * chi2 * r["dw"] ** 2 * d * r["M"] ** 2
+    flat = int(np.argmax(x > 1e-3 * tol)) if np.any(x > 1e-3 * tol) else nt + 1
+    want = flat if flat >= 2 else 0
+    assert r["n_t_merged"] == want
+    assert gp.plan_rules(d, nu, tol, lmin, lmax, 1.0, keep_t=1, **kw)["n_t_merged"] == 0
+    if want:
+        # the merged terms are constant over the box to 1e-3 tol: exp(-x) >= 1 - 1e-3 tol
+        assert np.all(1.0 - np.exp(-x[:want]) <= 1e-3 * tol)
