@@ -25,6 +25,7 @@ SOURCES = [
     ("gp_capi.hip", "gp_capi.o", []),
     ("gp_serve.hip", "gp_serve.o", []),
     ("gp_noalloc.hip", "gp_noalloc.o", []),
+    ("gp_rules.cpp", "gp_rules.o", []),
 ]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("GP_OFFLOAD_ARCH", "gfx950")

@@ -160,15 +160,6 @@ static int guarded(F&& f) {
 
 extern "C" {
 
-int gp_opts_init(gp_opts* o) {
-  if (!o) return GP_EINVAL;
-  std::memset(o, 0, sizeof(*o));
-  o->precision = GP_FP64;
-  o->n_sigma = -1;
-  o->n_t = -1;
-  return GP_OK;
-}
-
 int gp_plan(int d, int64_t n, const double* pts, const double* sigma, const double* l, double nu,
             double eta, double tol, const gp_opts* opts, gp_plan_t* out) {
   return guarded([&] {
@@ -270,8 +261,6 @@ int gp_plan_rules(int d, double nu, double tol, double l_min, double l_max, doub
     if (opts.l_lo > 0) lmin = std::min(lmin, opts.l_lo);
     if (opts.l_hi > 0) lmax = std::max(lmax, opts.l_hi);
     choose_params(&P, d, nu, tol, lmin, lmax, opts);
-    P.nk = P.n_sigma + 1;
-    P.npair = (P.nk + 1) / 2;
     fill_params(P, out);
     return GP_OK;
   });

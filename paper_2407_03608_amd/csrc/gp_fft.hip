@@ -434,16 +434,6 @@ void dispatch(const FftPass& q, const void* in, void* out, const void* tw, hipSt
 
 }  // namespace
 
-bool fft_length_supported(int L) {
-  switch (L) {
-    case 8: case 16: case 32: case 64: case 128: case 256: case 512: case 1024: case 2048:
-    case 4096: case 8192: case 24: case 48: case 96: case 192: case 384: case 768: case 1536:
-    case 3072: case 6144:
-      return true;
-    default:
-      return false;
-  }
-}
 
 void fft_pass(int fp64, const FftPass& p, const void* in, void* out, const void* twiddles,
               hipStream_t s) {

@@ -8,17 +8,13 @@
 #include <vector>
 
 #include "../../include/gpnufft.h"
+#include "gp_rules.h"
 
 namespace gp {
 
 // ------------------------------------------------------------------ errors --
 void set_error(const std::string& msg);
 void clear_error();
-
-struct Error {
-  int code;
-  std::string msg;
-};
 
 #define GP_HIP(call)                                                                    \
   do {                                                                                  \
@@ -41,9 +37,6 @@ struct DevBuf {
   void release();
   template <class T> T* as() const { return static_cast<T*>(p); }
 };
-
-// Lengths the FFT pass kernel is compiled for (2^a and 3*2^a, 8 .. 8192).
-bool fft_length_supported(int L);
 
 // One batched pass of 1-D FFTs along one axis of a strided array:
 // element (o, pos, c) of the input lives at in[o*in_os + i*inner + c] where
@@ -93,49 +86,11 @@ struct Records {
 };
 
 // ------------------------------------------------------------------- plan --
-struct Plan {
-  // problem
-  int d = 0;
+// A plan: its numbers (PlanRules, chosen on the host) and its device data.
+struct Plan : PlanRules {
   int64_t n = 0;
-  int precision = GP_FP64;
-  double nu = 0, eta = 0;
-  bool se = false;
+  double eta = 0;
   int device = 0;             // HIP device current when the plan was built
-  // mapping into [-1,1]^d
-  double center[3] = {0, 0, 0};
-  double scale = 1;
-  // approximation parameters (section 3.5)
-  double t_min = 0, t_max = 0;
-  int n_t = 0;
-  double s_min = 0, s_max = 0;
-  int n_sigma = 0;
-  double dw = 0;
-  int64_t M = 0;
-  double pred_tail = 0;
-  int m_capped = 0;
-  double l_range_lo = 0, l_range_hi = 0;  // admissible user length scales (mapped: *scale)
-  // spreading / FFT geometry
-  double nufft_tol = 0;
-  int w = 0;
-  double beta = 0;
-  double upsample = 2.0;
-  int nf[3] = {1, 1, 1};
-  int lo[3] = {0, 0, 0};
-  int na[3] = {1, 1, 1};      // active-box length (multiple of tile)
-  int tile[3] = {1, 1, 1};
-  int nbins[3] = {1, 1, 1};
-  int64_t n_bins = 1;
-  int nsrc = 2;               // source bins per dimension that reach a tile
-  int fourstep = 0;           // d = 1 and nf > 8192: nf = L1 * L2
-  int L1 = 0, L2 = 0;
-  int nk = 0;                 // real grids = N_sigma + 1
-  int npair = 0;              // complex grids = ceil(nk/2)
-  int nt_eff = 0;             // t nodes in the step-3 tables (N_t + 1 - n_flat + [n_flat > 0], or 1 for SE)
-  int n_flat = 0;             // leading t nodes merged into one constant term (0: none)
-  double tol = 0;             // the plan's accuracy target
-  int64_t mcount = 0;         // (2M+1)
-  // host copies of the tables (for info / tests)
-  std::vector<double> sig_nodes, bary, vt, chi;
   // device data
   hipStream_t stream = nullptr;
   Records rec;                // the training points, bin-sorted
@@ -150,8 +105,6 @@ struct Plan {
   double lr_rank_mean = 0;
   int spread_mode = GP_SPREAD_OWNER;  // resolved gp_opts.spread (never GP_SPREAD_AUTO)
   int interp_mode = 0;        // 0 default, 1 cache gather, 2 per-bin LDS tiles
-  int64_t a_rows = 0;         // distinct |n|^2 values (rows of A)
-  int nkp = 0;                // table width: nk rounded up to even
   DevBuf atab;                // T [a_rows][nkp(nkp+1)/2] upper triangle of A_k'k(|n|^2)
   DevBuf rowidx;              // int32 [d M^2 + 1]: |n|^2 -> row (d >= 2)
   DevBuf dec;                 // T [d][M+1] 1/psi^(2 pi n / nf_r)
@@ -209,8 +162,6 @@ struct PhaseScope {
 };
 
 // plan.hip
-void choose_params(Plan* P, int d, double nu, double tol, double lmin, double lmax,
-                   const gp_opts& opts);
 int build_plan(int d, int64_t n, const double* pts, const double* sigma, const double* l,
                double nu, double eta, double tol, const gp_opts* opts, Plan* P, bool query_only,
                size_t* bytes_out);

@@ -157,6 +157,26 @@ def test_window_grid_and_active_box(case):
         assert lo + na >= 0.5 * nf + nf * p["dw"] + 0.5 * p["w"]
 
 
+# Small grids of length 3*2^a (192, 96): a whole number of default tiles
+# (256 cells in 1-D) does not fit in the grid, so the tile is halved until one
+# does; the box must still hold every window.  These plans once got a box cut
+# to a power of two (128 of 192 cells) and failed at build time.
+@pytest.mark.parametrize("d,nu,tol,lmin,lmax,ups", [
+    (1, math.inf, 1e-4, 0.02, 0.04, 0.0),
+    (1, 2.5, 1e-4, 0.1, 0.1, 1.25),
+    (1, math.inf, 1e-6, 0.1, 0.1, 1.25),
+    (2, math.inf, 1e-4, 0.1, 0.1, 2.0),
+])
+def test_small_grid_active_box_holds_every_window(d, nu, tol, lmin, lmax, ups):
+    p = gp.plan_rules(d, nu, tol, lmin, lmax, 1.0, upsample=ups)
+    for r in range(d):
+        nf, lo, na, tile = p["nf"][r], p["lo"][r], p["na"][r], p["tile"][r]
+        assert tile & (tile - 1) == 0 and na % tile == 0 and 0 <= lo and lo + na <= nf
+        first = math.ceil(0.5 * nf - nf * p["dw"] - 0.5 * p["w"])
+        last = math.ceil(0.5 * nf + nf * p["dw"] - 0.5 * p["w"]) + p["w"]
+        assert lo <= first and last <= lo + na, (nf, lo, na, tile, p["w"])
+
+
 @pytest.mark.parametrize("case", CASES[:4], ids=IDS[:4])
 @pytest.mark.parametrize("ups", [1.25, 1.5])
 def test_upsampled_grid_and_window_rule(case, ups):
