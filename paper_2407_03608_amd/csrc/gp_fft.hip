@@ -176,7 +176,7 @@ constexpr int next_radix(int rem, int ept) {
 __device__ __forceinline__ int lpad(int p) { return p + (p >> 5); }
 
 struct KParams {
-  int64_t ntrans, inner, in_os, out_os;
+  int64_t ntrans, inner, in_os, out_os, in_es, in_cs, out_es, out_cs;
   int n_in, in_start, n_out, out_start, sign;
   int64_t L4, tw4_mod;
   int tw4_at_load;
@@ -293,8 +293,8 @@ __global__ __launch_bounds__(B*(L / EPT)) void fft_pass_kernel(
   const int64_t t = bid * B + b;
   const bool act = t < p.ntrans;
   const int64_t o = act ? t / p.inner : 0, c = act ? t - o * p.inner : 0;
-  const V* src = in + o * p.in_os + c;
-  V* dst = out + o * p.out_os + c;
+  const V* src = in + o * p.in_os + c * p.in_cs;
+  V* dst = out + o * p.out_os + c * p.out_cs;
   const int64_t row4 = tw4 != nullptr ? o % p.tw4_mod : 0;
   constexpr int R1 = next_radix(L, EPT);
   constexpr int NB1 = EPT / R1;
@@ -309,7 +309,7 @@ __global__ __launch_bounds__(B*(L / EPT)) void fft_pass_kernel(
       if (i < 0) i += L;
       V val = V{T(0), T(0)};
       if (act && i < p.n_in) {
-        val = src[(int64_t)i * p.inner];
+        val = src[(int64_t)i * p.in_es];
         if (tw4 != nullptr && p.tw4_at_load) {
           V wv = tw4[((int64_t)pos * row4) % p.L4];
           if (p.sign > 0) wv.y = -wv.y;
@@ -319,7 +319,7 @@ __global__ __launch_bounds__(B*(L / EPT)) void fft_pass_kernel(
       v[u * R1 + m] = val;
     }
   }
-  stages<T, V, L, EPT, 1>(v, buf + b * LP, jt, tw, p.sign, act, dst, p.inner, p, tw4, row4);
+  stages<T, V, L, EPT, 1>(v, buf + b * LP, jt, tw, p.sign, act, dst, p.out_es, p, tw4, row4);
 }
 
 constexpr int ept_for(int L) { return (L % 3 == 0) ? (L < 24 ? L : 24) : (L < 32 ? L : 32); }
@@ -342,6 +342,10 @@ void launch_len(const FftPass& q, const void* in, void* out, const void* tw, hip
   p.inner = q.inner;
   p.in_os = q.in_os;
   p.out_os = q.out_os;
+  p.in_es = q.in_es ? q.in_es : q.inner;
+  p.in_cs = q.in_cs ? q.in_cs : 1;
+  p.out_es = q.out_es ? q.out_es : q.inner;
+  p.out_cs = q.out_cs ? q.out_cs : 1;
   p.n_in = q.n_in;
   p.in_start = ((q.in_start % L) + L) % L;
   p.n_out = q.n_out;
