@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -88,6 +89,14 @@ struct Records {
   //           in order, each a contiguous range of the sorted points)
   DevBuf sp_work, sp_red, in_work, in_work2, part;
   int64_t n_sp_work = 0, n_sp_red = 0, n_in_work = 0, n_in_work2 = 0, n_slots = 0;
+  // Sub-tile spreading (fp32 grids, d >= 2; see build_spread_lists): sub-tiles
+  // of sub_st^d cells, numbered bin * (sub-tiles per bin) + sub, and for each
+  // the sorted indices of the points whose window reaches it:
+  //  sub_off   int64 [n_sub + 1]   start of each sub-tile's list
+  //  sub_list  int32 [sub_off[n_sub]]
+  DevBuf sub_off, sub_list;
+  int64_t n_sub = 0;
+  int sub_st = 0;
 };
 
 // ------------------------------------------------------------------- plan --
@@ -191,6 +200,19 @@ void posterior_sorted(Plan* P, const double* x_sorted, int64_t m, const double* 
 // writes ys = K~(points of R', those points) xs for any record set R'.
 void forward_from(Plan* P, const Records& R, const double* xs);
 void interp_from_grid(Plan* P, const Records& R, double* ys);
+// Spreading of fp32 grids in d >= 2 works on sub-tiles of spread_sub_side(P)^d
+// cells, one wavefront each, from per-sub-tile point lists built once per plan.
+inline bool spread_uses_sub_tiles(const Plan* P) {
+  return P->spread_mode != GP_SPREAD_LDS_ATOMIC && P->d >= 2 && P->precision == GP_FP32_BULK;
+}
+inline int spread_sub_side(const Plan* P) {
+  int st = P->d == 2 ? 8 : 4;
+  for (int r = 0; r < P->d; ++r) st = std::min(st, P->tile[r]);
+  return st;
+}
+// Device bytes of the sub-tile lists, bounded before the points are sorted.
+size_t spread_list_bound_bytes(const Plan* P, int64_t n);
+void build_spread_lists(Plan* P, Records& R);
 void build_records_into(Plan* P, int64_t n, const double* pts, const double* sig,
                         const double* l, Records& R, int* out_of_box);
 void gather_sorted(Plan* P, const double* x_user, double* x_sorted);

@@ -461,6 +461,7 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
   bytes += (size_t)n * (sizeof(int) * (1 + d) + ts * (d * P->w + P->nk + 1));
   bytes += (size_t)(P->n_bins + 1) * sizeof(int);
   bytes += work_list_bound_bytes(P, n, cs);
+  bytes += spread_list_bound_bytes(P, n);
   if (P->step3 != 1)  // the low-rank rows (step3 = 2) hold at most the full row's size
     bytes += (size_t)P->a_rows * (P->nkp * (P->nkp + 1) / 2) * ts + rowmap.size() * sizeof(int) +
              (P->step3 == 2 ? (size_t)(P->a_rows + 1) * sizeof(int64_t) : 0);
@@ -574,6 +575,7 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
   int oob = 0;
   build_records_into(P, n, pts, sigma, l, P->rec, &oob);
   if (oob) throw Error{GP_EDEVICE, "internal: a point's window left the active grid"};
+  build_spread_lists(P, P->rec);
 
   // ---- grids and vectors
   P->gridA.alloc((size_t)G * szA * cs);
