@@ -70,6 +70,8 @@ def parse():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the secondary workloads (d=1 N=2000, d=3 N=1e7)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--only", choices=["matern_3d"], default=None,
+                    help="run only this secondary workload (e.g. under a profiler) and print its line")
     ap.add_argument("--serving", action="store_true", help="serving benchmark instead of matvec steps")
     ap.add_argument("--requests", type=int, default=512)
     ap.add_argument("--rate", type=float, default=50.0)
@@ -186,6 +188,31 @@ def roofline(info, tm, steps):
             "avg_ms": round(ms, 4), "alg_bytes": b}
 
 
+def matern_3d_leg(gp, torch, args, steps=10, warmup=2):
+    """d=3 N=1e7 Gaussian-mixture nu=5/2 in fp32-bulk (spreading-heavy)."""
+    from paper_2407_03608_amd import inputs
+    log("secondary: matern_3d fp32-bulk")
+    p3 = inputs.matern_3d()
+    X, S, L, Y = (torch.as_tensor(v).to("cuda") for v in (p3.x, p3.sigma, p3.l, p3.y))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P = gp.Plan(X, S, L, p3.nu, p3.eta, 1e-4, precision=gp.GP_FP32_BULK, upsample=args.upsample)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    info = P.info()
+    t, tm = time_path(gp, torch, P, Y, steps, warmup)
+    rf = roofline(info, tm, steps)
+    out = {
+        "workload": "d=3 N=1e7 8-component Gaussian mixture clipped to [0,1]^3, nu=5/2, sigma=1, "
+                    "l=0.03+0.02|x-0.5|, eta=0.1, fp32-bulk tol 1e-4",
+        "ms_per_step": round(1e3 * t / steps, 4), "points_per_s": round(p3.n * steps / t, 1),
+        "roofline": rf, "kernels_ms": {k: round(v[1] / steps, 4) for k, v in tm.items() if v[0]},
+        "plan_seconds": round(tp, 3),
+        "plan": {k: info[k] for k in ("n_sigma", "n_t", "dw", "M", "nf", "w", "upsample", "na", "n_pairs", "device_bytes")}}
+    P.close()
+    return out
+
+
 def secondary_workloads(gp, torch, args):
     """The other measured configurations, reported beside the headline:
     d=1 N=2000 nu=3/2 fp64 (launch-bound; full solve to 1e-8) and d=3 N=1e7
@@ -212,27 +239,7 @@ def secondary_workloads(gp, torch, args):
         "plan": {k: info[k] for k in ("n_sigma", "n_t", "dw", "M", "nf", "w", "upsample")}}
     P.close()
     del X, S, L, Y
-    log("secondary: matern_3d fp32-bulk")
-    p3 = inputs.matern_3d()
-    X, S, L, Y = (torch.as_tensor(v).to(dev) for v in (p3.x, p3.sigma, p3.l, p3.y))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    P = gp.Plan(X, S, L, p3.nu, p3.eta, 1e-4, precision=gp.GP_FP32_BULK, upsample=args.upsample)
-    torch.cuda.synchronize()
-    tp = time.perf_counter() - t0
-    info = P.info()
-    steps = 10
-    t, tm = time_path(gp, torch, P, Y, steps, 2)
-    rf = roofline(info, tm, steps)
-    out["matern_3d_fp32_bulk"] = {
-        "workload": "d=3 N=1e7 8-component Gaussian mixture clipped to [0,1]^3, nu=5/2, sigma=1, "
-                    "l=0.03+0.02|x-0.5|, eta=0.1, fp32-bulk tol 1e-4",
-        "ms_per_step": round(1e3 * t / steps, 4), "points_per_s": round(p3.n * steps / t, 1),
-        "roofline": rf, "kernels_ms": {k: round(v[1] / steps, 4) for k, v in tm.items() if v[0]},
-        "plan_seconds": round(tp, 3),
-        "plan": {k: info[k] for k in ("n_sigma", "n_t", "dw", "M", "nf", "w", "upsample", "na", "n_pairs", "device_bytes")}}
-    P.close()
-    del X, S, L, Y
+    out["matern_3d_fp32_bulk"] = matern_3d_leg(gp, torch, args)
     out["multi_rhs_cg"] = multi_rhs_leg(gp, torch, inputs)
     return out
 
@@ -522,6 +529,18 @@ def main():
 
     assert torch.cuda.is_available()
     dev = "cuda"
+    if args.only == "matern_3d":
+        out = matern_3d_leg(gp, torch, args, steps=args.steps, warmup=args.warmup)
+        if args.calib_copy_mib:
+            nb = args.calib_copy_mib * (1 << 20) // 8
+            src = torch.ones(nb, dtype=torch.float64, device=dev)
+            dst = torch.empty_like(src)
+            torch.cuda.synchronize()
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            out["calib_copy_bytes"] = nb * 8
+        print(json.dumps(out), flush=True)
+        return
     log("generating inputs")
     prob = inputs.matern_2d(n=args.n)
     X = torch.as_tensor(prob.x).to(dev)

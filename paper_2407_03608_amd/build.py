@@ -19,6 +19,7 @@ SOURCES = [
     ("gp_fft.hip", "gp_fft.o", []),
     ("gp_plan.hip", "gp_plan.o", []),
     ("gp_nufft.hip", "gp_nufft.o", []),
+    ("gp_spread.hip", "gp_spread.o", []),
     ("gp_mode.hip", "gp_mode64.o", ["-DGP_MODE_FP64=1"]),
     ("gp_mode.hip", "gp_mode32.o", ["-DGP_MODE_FP64=0"]),
     ("gp_cg.hip", "gp_cg.o", []),

@@ -453,6 +453,7 @@ int gp_posterior_cov(gp_plan_t h, int64_t m, const double* targets, const double
     int oob = 0;
     build_records_into(P, m, targets, sigma_t, l_t, T, &oob);
     if (oob) throw Error{GP_ERANGE, "target outside the plan's box"};
+    build_spread_lists(P, T);  // the targets are spread for K~(x*, .)
     std::vector<int> perm(m), inv(m);
     GP_HIP(hipMemcpyAsync(perm.data(), T.perm.p, m * sizeof(int), hipMemcpyDeviceToHost, s));
     GP_HIP(hipStreamSynchronize(s));

@@ -91,9 +91,10 @@ struct Records {
   int64_t n_sp_work = 0, n_sp_red = 0, n_in_work = 0, n_in_work2 = 0, n_slots = 0;
   // Sub-tile spreading (fp32 grids, d >= 2; see build_spread_lists): sub-tiles
   // of sub_st^d cells, numbered bin * (sub-tiles per bin) + sub, and for each
-  // the sorted indices of the points whose window reaches it:
+  // the points whose window reaches it, in visiting order:
   //  sub_off   int64 [n_sub + 1]   start of each sub-tile's list
-  //  sub_list  int32 [sub_off[n_sub]]
+  //  sub_list  int2 [sub_off[n_sub]]  {sorted index, first window cell
+  //            relative to the sub-tile origin - (w - 1), 8 bits per dimension}
   DevBuf sub_off, sub_list;
   int64_t n_sub = 0;
   int sub_st = 0;
@@ -200,19 +201,34 @@ void posterior_sorted(Plan* P, const double* x_sorted, int64_t m, const double* 
 // writes ys = K~(points of R', those points) xs for any record set R'.
 void forward_from(Plan* P, const Records& R, const double* xs);
 void interp_from_grid(Plan* P, const Records& R, double* ys);
-// Spreading of fp32 grids in d >= 2 works on sub-tiles of spread_sub_side(P)^d
-// cells, one wavefront each, from per-sub-tile point lists built once per plan.
-inline bool spread_uses_sub_tiles(const Plan* P) {
-  return P->spread_mode != GP_SPREAD_LDS_ATOMIC && P->d >= 2 && P->precision == GP_FP32_BULK;
-}
-inline int spread_sub_side(const Plan* P) {
-  int st = P->d == 2 ? 8 : 4;
-  for (int r = 0; r < P->d; ++r) st = std::min(st, P->tile[r]);
-  return st;
-}
+// Kernel arguments of the spreading and interpolation kernels for one point
+// set (training points or targets) and one chunk of grid pairs.
+struct NuArgs {
+  int64_t n;
+  int nk, npair, w;
+  double beta;
+  int tile[3], nbins[3], na[3];
+  int64_t gstride[3];  // element strides of the active grid (dim 0 contiguous)
+  int64_t pair_stride;
+  int64_t grid_off;
+  int g0, gc, nsrc;
+  int slot_pairs;  // grid pairs per partial tile slot (min(8, npair))
+  double eta2;
+  int add_noise, first_chunk;
+};
+NuArgs nu_args(const Plan* P, const Records& R);
+// Grid A (spread output, interpolation input) of the current vector set.
+void* grid_a_current(const Plan* P);
+
+// Spreading in d >= 2 works on sub-tiles of spread_sub_side(P)^d cells, one
+// wavefront each, from per-sub-tile point lists built once per plan
+// (gp_spread.hip); other plans spread whole tiles.
+int spread_sub_side(const Plan* P);  // 0 when the plan spreads whole tiles
+inline bool spread_uses_sub_tiles(const Plan* P) { return spread_sub_side(P) > 0; }
 // Device bytes of the sub-tile lists, bounded before the points are sorted.
 size_t spread_list_bound_bytes(const Plan* P, int64_t n);
 void build_spread_lists(Plan* P, Records& R);
+void spread_sub_launch(Plan* P, const Records& R, const double* xs);
 void build_records_into(Plan* P, int64_t n, const double* pts, const double* sig,
                         const double* l, Records& R, int* out_of_box);
 void gather_sorted(Plan* P, const double* x_user, double* x_sorted);

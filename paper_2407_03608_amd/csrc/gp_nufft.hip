@@ -51,19 +51,6 @@ constexpr int kPB = 64;      // points staged per batch
 constexpr int kGC = 8;       // max complex grids per chunk
 constexpr int kRG = 4;       // interpolation row groups per (point, grid pair)
 
-struct NuArgs {
-  int64_t n;
-  int nk, npair, w;
-  double beta;
-  int tile[3], nbins[3], na[3];
-  int64_t gstride[3];  // element strides of the active grid (dim 0 contiguous)
-  int64_t pair_stride;
-  int64_t grid_off;
-  int g0, gc, nsrc;
-  int slot_pairs;  // grid pairs per partial tile slot (min(kGC, npair))
-  double eta2;
-  int add_noise, first_chunk;
-};
 
 // Points are staged in LDS in batches of kPB: the first window cell per
 // dimension, the point's row of window values and weights (padded to an odd
@@ -280,207 +267,6 @@ __global__ __launch_bounds__(kThreads) void spread_reduce_kernel(
                        (int64_t)c2 * a.gstride[2];
     grid[(int64_t)(a.g0 + g) * a.pair_stride + gi] = v;
   }
-}
-
-// ----------------------------------------------------- spread (sub-tiles) ----
-// Owner-computes on sub-tiles of st^D cells (st = 8 in 2-D, 4 in 3-D) with one
-// wavefront per sub-tile and one cell per lane.  A point costs one
-// wavefront-step per sub-tile its window reaches instead of every thread of a
-// whole tile.  The points that reach each sub-tile are listed once per plan
-// (spread_list_build_kernel, in the order the sorted points are visited), so
-// a matvec streams exactly the contributing points of its sub-tile; the
-// summation order of every cell is that list order (bitwise reproducible).
-constexpr int kSubThreads = 64;
-
-// Sub-tile blk = bin * nsub + sub (sub-tiles of a bin consecutive, first
-// dimension fastest): its first cell s0, its bin's coordinates tcoord.
-__device__ __forceinline__ void sub_tile_origin(const NuArgs& a, int D, int st, int64_t blk,
-                                                int* s0, int* tcoord) {
-  int nsub = 1;
-  for (int r = 0; r < D; ++r) nsub *= a.tile[r] / st;  // st divides every tile side
-  int64_t tb = blk / nsub;
-  int sub = (int)(blk % nsub);
-  for (int r = 0; r < 3; ++r) {
-    s0[r] = 0;
-    tcoord[r] = 0;
-  }
-  for (int r = 0; r < D; ++r) {
-    const int per = a.tile[r] / st;
-    tcoord[r] = (int)(tb % a.nbins[r]);
-    tb /= a.nbins[r];
-    s0[r] = tcoord[r] * a.tile[r] + (sub % per) * st;
-    sub /= per;
-  }
-}
-
-// Workgroups go to the 8 XCDs round-robin by id.  Sub-tiles are dealt to the
-// XCDs in groups of `grp` consecutive ones (the sub-tiles of the bins that
-// share cache lines of grid rows), so each group is written through one L2,
-// while the groups still alternate between XCDs (clustered points keep every
-// XCD equally busy).  The grid is padded to a multiple of 8 grp workgroups;
-// the map is a bijection onto [0, gridDim.x) and ids >= the sub-tile count
-// have no work.
-__device__ __forceinline__ int64_t xcd_grouped(int64_t bid, int grp) {
-  const int64_t x = bid % 8, k = bid / 8;
-  return ((k / grp) * 8 + x) * grp + k % grp;
-}
-
-// Plan time, one wavefront per sub-tile: walk the concatenated source bins
-// (the tile's bin and its lower neighbours within w-1 cells, first dimension
-// fastest, without the bins none of whose points reach this sub-tile: along
-// dimension r the points of the bin dq >= 1 tiles below start at most at
-// t0 - (dq - 1) tile - 1, so their windows end before s0 when that
-// start + w - 1 < s0), keep the points whose window reaches the sub-tile in
-// every dimension, and either count them (FILL = false) or write their sorted
-// indices at list[off[blk] ..] in visiting order (FILL = true).
-template <int D, bool FILL>
-__global__ __launch_bounds__(kSubThreads) void spread_list_build_kernel(
-    NuArgs a, int st, const int* __restrict__ cell, const int* __restrict__ bin_start,
-    int* __restrict__ cnt, const int64_t* __restrict__ off, int* __restrict__ list) {
-  extern __shared__ int ismem[];
-  const int64_t blk = blockIdx.x;
-  int s0[3], tcoord[3];
-  sub_tile_origin(a, D, st, blk, s0, tcoord);
-  const int w = a.w;
-  int nsrc_tot = 1;
-  for (int r = 0; r < D; ++r) nsrc_tot *= a.nsrc;
-  int* s_sb0 = ismem;              // [nsrc_tot]
-  int* s_soff = s_sb0 + nsrc_tot;  // [nsrc_tot + 1]
-  for (int sb = threadIdx.x; sb < nsrc_tot; sb += kSubThreads) {
-    int64_t b = 0, mul = 1;
-    bool ok = true;
-    int q = sb;
-    for (int r = 0; r < D; ++r) {
-      const int dq = q % a.nsrc;
-      const int br = tcoord[r] - dq;
-      q /= a.nsrc;
-      if (br < 0) ok = false;
-      if (dq > 0 && tcoord[r] * a.tile[r] - (dq - 1) * a.tile[r] - 1 + w - 1 < s0[r]) ok = false;
-      b += (int64_t)br * mul;
-      mul *= a.nbins[r];
-    }
-    const int b0 = ok ? bin_start[b] : 0;
-    s_sb0[sb] = b0;
-    s_soff[sb + 1] = ok ? bin_start[b + 1] - b0 : 0;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    s_soff[0] = 0;
-    for (int sb = 0; sb < nsrc_tot; ++sb) s_soff[sb + 1] += s_soff[sb];
-  }
-  __syncthreads();
-  const int seq_hi = s_soff[nsrc_tot];
-  int64_t count = 0;
-  const int64_t o = FILL ? off[blk] : 0;
-  for (int base = 0; base < seq_hi; base += kSubThreads) {
-    const int qpos = base + (int)threadIdx.x;
-    bool keep = qpos < seq_hi;
-    int idx = 0;
-    if (keep) {
-      int sb = 0;
-      while (qpos >= s_soff[sb + 1]) ++sb;
-      idx = s_sb0[sb] + (qpos - s_soff[sb]);
-      int cr[3];
-      for (int r = 0; r < D; ++r) cr[r] = cell[r * a.n + idx];
-      for (int r = 0; r < D; ++r) keep = keep & (cr[r] + w - 1 >= s0[r]) & (cr[r] < s0[r] + st);
-    }
-    const unsigned long long m = __ballot(keep);
-    if (FILL && keep) list[o + count + __popcll(m & ((1ull << threadIdx.x) - 1ull))] = idx;
-    count += __popcll(m);
-  }
-  if (!FILL && threadIdx.x == 0) cnt[blk] = (int)count;
-}
-
-// One wavefront per sub-tile, one cell per lane.  Batches of up to 64 listed
-// points are staged in LDS: per point its first window cell relative to the
-// sub-tile (one packed word), the dimension-0 window values times x_i, the
-// other dimensions' window values, and the chunk's 2 GC weights w_k (aligned,
-// read as vectors); each lane adds the staged points whose window covers its
-// cell.  The products are formed in the order (psi_0 x) psi_1 psi_2.
-template <typename T>
-__host__ __device__ constexpr int sub_stage_stride(int D, int w, int gc) {
-  return ((((D * w + 3) / 4) * 4 + 2 * gc + 3) / 4) * 4;
-}
-template <typename T, int D, int GC>
-__global__ __launch_bounds__(kSubThreads) void spread_list_kernel(
-    NuArgs a, int st, int grp, int64_t nsub, const double* __restrict__ x,
-    const int* __restrict__ cell, const T* __restrict__ pw, int rs,
-    const int64_t* __restrict__ off, const int* __restrict__ list,
-    typename V2<T>::type* __restrict__ grid) {
-  using V = typename V2<T>::type;
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int w = a.w;
-  const int SW = ((D * w + 3) / 4) * 4;  // first weight column (16-byte aligned for float)
-  const int SS = sub_stage_stride<T>(D, w, GC);
-  T* s_v = reinterpret_cast<T*>(smem);                       // [kSubThreads][SS]
-  int* s_cw = reinterpret_cast<int*>(s_v + kSubThreads * SS);  // [kSubThreads]
-  int* s_map = s_cw + kSubThreads;                             // [kSubThreads]
-  T* s_x = reinterpret_cast<T*>(s_map + kSubThreads);          // [kSubThreads]
-
-  const int64_t blk = xcd_grouped(blockIdx.x, grp);
-  if (blk >= nsub) return;
-  int s0[3], tcoord[3];
-  sub_tile_origin(a, D, st, blk, s0, tcoord);
-  int l = threadIdx.x;
-  int lr[3] = {0, 0, 0}, c[3] = {0, 0, 0};
-  for (int r = 0; r < D; ++r) {
-    c[r] = s0[r] + l % st;
-    lr[r] = l % st + w - 1;  // the lane's cell relative to s0 - (w - 1)
-    l /= st;
-  }
-  const bool mine = l == 0;  // lanes beyond st^D own no cell
-  V acc[GC];
-#pragma unroll
-  for (int g = 0; g < GC; ++g) acc[g] = V{T(0), T(0)};
-  const int wko = D * w + 2 * a.g0;
-  const int ncol = D * w + 2 * GC;
-  const int64_t lo = off[blk], hi = off[blk + 1];
-  for (int64_t base = lo; base < hi; base += kSubThreads) {
-    const int np = (int)min((int64_t)kSubThreads, hi - base);
-    __syncthreads();
-    if ((int)threadIdx.x < np) {
-      const int i = list[base + threadIdx.x];
-      s_map[threadIdx.x] = i;
-      s_x[threadIdx.x] = (T)x[i];
-      int cw = 0;
-      for (int r = 0; r < D; ++r) cw |= (cell[r * a.n + i] - s0[r] + w - 1) << (8 * r);
-      s_cw[threadIdx.x] = cw;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < np * ncol; e += kSubThreads) {
-      const int p = e / ncol, cc = e - p * ncol;
-      const bool win = cc < D * w;
-      T v = pw[(int64_t)s_map[p] * rs + (win ? cc : wko + cc - D * w)];
-      if (cc < w) v *= s_x[p];
-      s_v[p * SS + (win ? cc : SW + cc - D * w)] = v;
-    }
-    __syncthreads();
-    for (int p = 0; p < np; ++p) {
-      const int cw = s_cw[p];
-      const unsigned d0 = (unsigned)(lr[0] - (cw & 255));
-      const unsigned d1 = (unsigned)(lr[1] - ((cw >> 8) & 255));
-      const unsigned d2 = D > 2 ? (unsigned)(lr[2] - ((cw >> 16) & 255)) : 0u;
-      bool hit = d0 < (unsigned)w && d1 < (unsigned)w;
-      if (D > 2) hit = hit && d2 < (unsigned)w;
-      if (hit) {
-        const T* pv = s_v + p * SS;
-        T v = pv[d0] * pv[w + d1];
-        if (D > 2) v *= pv[2 * w + d2];
-        const V* pg = reinterpret_cast<const V*>(pv + SW);
-#pragma unroll
-        for (int g = 0; g < GC; ++g) {
-          const V wk = pg[g];
-          acc[g].x += v * wk.x;
-          acc[g].y += v * wk.y;
-        }
-      }
-    }
-  }
-  if (!mine) return;
-  const int64_t gi = a.grid_off + (int64_t)c[0] * a.gstride[0] + (int64_t)c[1] * a.gstride[1] +
-                     (int64_t)c[2] * a.gstride[2];
-#pragma unroll
-  for (int g = 0; g < GC; ++g) grid[(int64_t)(a.g0 + g) * a.pair_stride + gi] = acc[g];
 }
 
 // ---------------------------------------------------------------- spread ----
@@ -952,72 +738,6 @@ __global__ void scatter_kernel(int64_t n, const int* __restrict__ perm, const do
   if (i < n) u[perm[i]] = s[i];
 }
 
-// ------------------------------------------------------------------ scan ----
-// Exclusive prefix sum of int counts into int64 offsets, out[n] = total; 1024
-// elements per workgroup (4 per thread), the workgroup totals scanned the
-// same way and added back.
-constexpr int kScanThreads = 256, kScanPer = 4, kScanBlock = kScanThreads * kScanPer;
-template <typename In>
-__global__ __launch_bounds__(kScanThreads) void scan_block_kernel(const In* __restrict__ in, int64_t n,
-                                                                  int64_t* __restrict__ out,
-                                                                  int64_t* __restrict__ sums) {
-  __shared__ int64_t s[kScanThreads];
-  const int64_t b0 = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanPer;
-  int64_t v[kScanPer], t = 0;
-  for (int k = 0; k < kScanPer; ++k) {
-    v[k] = b0 + k < n ? (int64_t)in[b0 + k] : 0;
-    t += v[k];
-  }
-  s[threadIdx.x] = t;
-  __syncthreads();
-  for (int d = 1; d < kScanThreads; d *= 2) {
-    const int64_t add = threadIdx.x >= d ? s[threadIdx.x - d] : 0;
-    __syncthreads();
-    s[threadIdx.x] += add;
-    __syncthreads();
-  }
-  int64_t run = s[threadIdx.x] - t;  // exclusive prefix of this thread
-  for (int k = 0; k < kScanPer; ++k) {
-    if (b0 + k < n) out[b0 + k] = run;
-    run += v[k];
-  }
-  if (threadIdx.x == kScanThreads - 1) sums[blockIdx.x] = s[threadIdx.x];
-}
-__global__ __launch_bounds__(kScanThreads) void scan_add_kernel(int64_t* __restrict__ out, int64_t n,
-                                                                const int64_t* __restrict__ offs) {
-  const int64_t i = (int64_t)blockIdx.x * kScanThreads + threadIdx.x;
-  if (i < n) out[i] += offs[i / kScanBlock];
-}
-
-// out[0..n) = exclusive prefix sums of in[0..n); returns the total (one
-// device-to-host read at the end; plan time only).
-template <typename In>
-void exclusive_scan(const In* in, int64_t n, int64_t* out, hipStream_t s, int64_t* total) {
-  const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
-  DevBuf sums, soff;
-  sums.alloc((size_t)std::max<int64_t>(nb, 1) * sizeof(int64_t));
-  if (n > 0) {
-    hipLaunchKernelGGL((scan_block_kernel<In>), dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n,
-                       out, sums.as<int64_t>());
-    GP_CHECK_LAUNCH();
-  }
-  if (nb > 1) {
-    soff.alloc((size_t)nb * sizeof(int64_t));
-    int64_t sub_total = 0;
-    exclusive_scan<int64_t>(sums.as<int64_t>(), nb, soff.as<int64_t>(), s, &sub_total);
-    hipLaunchKernelGGL(scan_add_kernel, dim3((unsigned)((n + kScanThreads - 1) / kScanThreads)),
-                       dim3(kScanThreads), 0, s, out, n, soff.as<int64_t>());
-    GP_CHECK_LAUNCH();
-    *total = sub_total;
-    GP_HIP(hipStreamSynchronize(s));  // sums and soff are released on return
-    return;
-  }
-  int64_t t = 0;
-  if (n > 0) GP_HIP(hipMemcpyAsync(&t, sums.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  GP_HIP(hipStreamSynchronize(s));
-  *total = t;
-}
-
 // ------------------------------------------------------------- launchers ----
 template <typename T>
 size_t spread_smem(const Plan* P, int gc, int rs) {
@@ -1048,38 +768,6 @@ size_t interp_smem(const Plan* P, int gc, int rs) {
 
 constexpr size_t kSmemCap = 64 * 1024;
 
-// Kernel arguments for the point set R (training points or targets) of plan P.
-NuArgs nu_args(const Plan* P, const Records& R) {
-  NuArgs a;
-  a.n = R.n;
-  a.nk = P->nk;
-  a.npair = P->npair;
-  a.w = P->w;
-  a.beta = P->beta;
-  for (int r = 0; r < 3; ++r) {
-    a.tile[r] = P->tile[r];
-    a.nbins[r] = P->nbins[r];
-    a.na[r] = P->na[r];
-  }
-  a.gstride[0] = 1;
-  a.gstride[1] = P->d > 1 ? P->na[0] : 0;
-  a.gstride[2] = P->d > 2 ? (int64_t)P->na[0] * P->na[1] : 0;
-  if (P->d == 1) {
-    a.pair_stride = P->fourstep ? P->nf[0] : P->na[0];
-    a.grid_off = P->fourstep ? P->lo[0] : 0;
-  } else {
-    a.pair_stride = (int64_t)P->na[0] * P->na[1] * P->na[2];
-    a.grid_off = 0;
-  }
-  a.nsrc = P->nsrc;
-  a.slot_pairs = std::min(kGC, P->npair);
-  a.g0 = 0;
-  a.gc = 0;
-  a.eta2 = P->eta * P->eta;
-  a.add_noise = 0;
-  a.first_chunk = 1;
-  return a;
-}
 
 // Grid A (spread output, interpolation input) of the current vector set.
 template <typename V>
@@ -1189,46 +877,13 @@ void launch_interp(Plan* P, const Records& R, const double* xs, double* ys, int 
   }
 }
 
-template <typename T, int D>
-void launch_spread_sub(Plan* P, const Records& R, const double* xs) {
-  PhaseScope ps(P, PH_SPREAD);
-  NuArgs a = nu_args(P, R);
-  const int gc = std::min(kGC, P->npair);
-  const int nch = (P->npair + gc - 1) / gc;
-  if (R.n_sub <= 0) return;
-  // groups: the sub-tiles of one bin (2-D: its rows of 16 fp32 pairs are one
-  // 128-byte line) or of two bins along dimension 0 (3-D: 8-cell rows)
-  int grp = 1;
-  for (int r = 0; r < D; ++r) grp *= P->tile[r] / R.sub_st;
-  if (D == 3 && P->nbins[0] % 2 == 0) grp *= 2;
-  const int64_t nblk = (R.n_sub + 8 * grp - 1) / (8 * grp) * (8 * grp);
-  for (int ch = 0; ch < nch; ++ch) {
-    a.g0 = ch * gc;
-    a.gc = std::min(gc, P->npair - a.g0);
-    const size_t smem = kSubThreads * (sub_stage_stride<T>(D, P->w, a.gc) + 1) * sizeof(T) +
-                        2 * kSubThreads * sizeof(int);
-#define GP_LAUNCH_SUB(GCV)                                                                    \
-  hipLaunchKernelGGL((spread_list_kernel<T, D, GCV>), dim3((unsigned)nblk), dim3(kSubThreads),    \
-                     smem, P->stream, a, R.sub_st, grp, R.n_sub, xs, R.cell.as<int>(),          \
-                     R.pw.as<T>(), R.rs,                                                        \
-                     R.sub_off.as<int64_t>(), R.sub_list.as<int>(),                             \
-                     cur_gridA<typename V2<T>::type>(P))
-    GP_GC_SWITCH(a.gc, GP_LAUNCH_SUB)
-#undef GP_LAUNCH_SUB
-    GP_CHECK_LAUNCH();
-  }
-}
-
 template <typename T>
 void spread_dispatch(Plan* P, const Records& R, const double* xs) {
   const int tcells = P->tile[0] * P->tile[1] * P->tile[2];
   const int mode = P->spread_mode;
-  // fp32 grids in d >= 2: one wavefront per sub-tile (measured 4-7 % faster
-  // there; 2x slower for fp64, whose 16-byte rows make the staging dominate)
-  if (spread_uses_sub_tiles(P)) {
-    if (R.n_sub <= 0) throw Error{GP_EDEVICE, "internal: sub-tile lists missing"};
-    if (P->d == 2) launch_spread_sub<T, 2>(P, R, xs);
-    else launch_spread_sub<T, 3>(P, R, xs);
+  // d >= 2: one wavefront per sub-tile from the point set's per-sub-tile lists
+  if (spread_uses_sub_tiles(P) && R.n_sub > 0) {
+    spread_sub_launch(P, R, xs);
     return;
   }
   if (mode != GP_SPREAD_LDS_ATOMIC && tcells <= 2 * kThreads) {
@@ -1449,6 +1104,44 @@ void forward_and_mix(Plan* P, const Records& R, const double* xs) {
 
 }  // namespace
 
+// Kernel arguments for the point set R (training points or targets) of plan P.
+NuArgs nu_args(const Plan* P, const Records& R) {
+  NuArgs a;
+  a.n = R.n;
+  a.nk = P->nk;
+  a.npair = P->npair;
+  a.w = P->w;
+  a.beta = P->beta;
+  for (int r = 0; r < 3; ++r) {
+    a.tile[r] = P->tile[r];
+    a.nbins[r] = P->nbins[r];
+    a.na[r] = P->na[r];
+  }
+  a.gstride[0] = 1;
+  a.gstride[1] = P->d > 1 ? P->na[0] : 0;
+  a.gstride[2] = P->d > 2 ? (int64_t)P->na[0] * P->na[1] : 0;
+  if (P->d == 1) {
+    a.pair_stride = P->fourstep ? P->nf[0] : P->na[0];
+    a.grid_off = P->fourstep ? P->lo[0] : 0;
+  } else {
+    a.pair_stride = (int64_t)P->na[0] * P->na[1] * P->na[2];
+    a.grid_off = 0;
+  }
+  a.nsrc = P->nsrc;
+  a.slot_pairs = std::min(kGC, P->npair);
+  a.g0 = 0;
+  a.gc = 0;
+  a.eta2 = P->eta * P->eta;
+  a.add_noise = 0;
+  a.first_chunk = 1;
+  return a;
+}
+
+void* grid_a_current(const Plan* P) {
+  const size_t cs = P->precision == GP_FP64 ? 16 : 8;
+  return static_cast<char*>(P->gv.A) + (size_t)P->gv.cur * P->npair * P->grid_elems[0] * cs;
+}
+
 void matvec_sorted(Plan* P, const double* xs, double* ys, int add_noise) {
   if (P->precision == GP_FP64) {
     forward_and_mix<double>(P, P->rec, xs);
@@ -1457,64 +1150,6 @@ void matvec_sorted(Plan* P, const double* xs, double* ys, int add_noise) {
     forward_and_mix<float>(P, P->rec, xs);
     interp_dispatch<float>(P, P->rec, xs, ys, add_noise);
   }
-}
-
-size_t spread_list_bound_bytes(const Plan* P, int64_t n) {
-  if (!spread_uses_sub_tiles(P)) return 0;
-  const int st = spread_sub_side(P);
-  int64_t per_point = 1, nsub = P->n_bins;
-  for (int r = 0; r < P->d; ++r) {
-    per_point *= (P->w - 2 + st) / st + 1;  // sub-tiles one window spans, at most
-    nsub *= P->tile[r] / st;
-  }
-  return (size_t)n * per_point * sizeof(int) + (size_t)(2 * nsub + 1) * sizeof(int64_t);
-}
-
-// The exact source lists of sub-tile spreading, built on the device from the
-// sorted points: count per sub-tile, scan, fill (both passes visit the points
-// in the same order, so the lists and every later sum are deterministic).
-void build_spread_lists(Plan* P, Records& R) {
-  R.n_sub = 0;
-  if (!spread_uses_sub_tiles(P)) return;
-  hipStream_t s = P->stream;
-  const int st = spread_sub_side(P);
-  for (int r = 0; r < P->d; ++r)
-    if (P->tile[r] % st != 0) throw Error{GP_EDEVICE, "internal: sub-tile does not divide the tile"};
-  int64_t nsub = P->n_bins;
-  for (int r = 0; r < P->d; ++r) nsub *= P->tile[r] / st;
-  if (nsub > (int64_t)std::numeric_limits<int>::max()) throw Error{GP_ENOMEM, "too many sub-tiles"};
-  NuArgs a = nu_args(P, R);
-  int nsrc_tot = 1;
-  for (int r = 0; r < P->d; ++r) nsrc_tot *= P->nsrc;
-  const size_t smem = (2 * (size_t)nsrc_tot + 1) * sizeof(int);
-  DevBuf cnt;
-  cnt.alloc((size_t)nsub * sizeof(int));
-  R.sub_off.alloc((size_t)(nsub + 1) * sizeof(int64_t));
-  if (P->d == 2)
-    hipLaunchKernelGGL((spread_list_build_kernel<2, false>), dim3((unsigned)nsub), dim3(kSubThreads), smem,
-                       s, a, st, R.cell.as<int>(), R.bin_start.as<int>(), cnt.as<int>(), nullptr, nullptr);
-  else
-    hipLaunchKernelGGL((spread_list_build_kernel<3, false>), dim3((unsigned)nsub), dim3(kSubThreads), smem,
-                       s, a, st, R.cell.as<int>(), R.bin_start.as<int>(), cnt.as<int>(), nullptr, nullptr);
-  GP_CHECK_LAUNCH();
-  int64_t total = 0;
-  exclusive_scan<int>(cnt.as<int>(), nsub, R.sub_off.as<int64_t>(), s, &total);
-  GP_HIP(hipMemcpyAsync(R.sub_off.as<int64_t>() + nsub, &total, sizeof(int64_t), hipMemcpyHostToDevice, s));
-  const size_t bound = spread_list_bound_bytes(P, R.n);
-  if ((size_t)total * sizeof(int) > bound) throw Error{GP_EDEVICE, "internal: sub-tile lists over their bound"};
-  R.sub_list.alloc((size_t)std::max<int64_t>(total, 1) * sizeof(int));
-  if (P->d == 2)
-    hipLaunchKernelGGL((spread_list_build_kernel<2, true>), dim3((unsigned)nsub), dim3(kSubThreads), smem,
-                       s, a, st, R.cell.as<int>(), R.bin_start.as<int>(), nullptr,
-                       R.sub_off.as<int64_t>(), R.sub_list.as<int>());
-  else
-    hipLaunchKernelGGL((spread_list_build_kernel<3, true>), dim3((unsigned)nsub), dim3(kSubThreads), smem,
-                       s, a, st, R.cell.as<int>(), R.bin_start.as<int>(), nullptr,
-                       R.sub_off.as<int64_t>(), R.sub_list.as<int>());
-  GP_CHECK_LAUNCH();
-  GP_HIP(hipStreamSynchronize(s));  // &total is a host stack value
-  R.n_sub = nsub;
-  R.sub_st = st;
 }
 
 int multi_capacity(Plan* P, int want) {
