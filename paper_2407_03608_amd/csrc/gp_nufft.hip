@@ -574,7 +574,9 @@ constexpr int kPB2 = (D > 2 && sizeof(T) == 4) ? 320 : 128;
 template <int D>
 constexpr int kTE = D > 2 ? 20 : 8;
 
-template <typename T, bool PIPE, int D>
+// W > 0: the window width as a compile-time constant (inner loops unrolled);
+// W = 0 reads it from the arguments.
+template <typename T, bool PIPE, int D, int W>
 __global__ __launch_bounds__(kThreads) void interp_super_kernel(
     NuArgs a, const typename V2<T>::type* __restrict__ grid, const int* __restrict__ cell,
     const T* __restrict__ pw, int rs, const int* __restrict__ bin_start,
@@ -583,7 +585,7 @@ __global__ __launch_bounds__(kThreads) void interp_super_kernel(
   constexpr int PB = kPB2<D, T>;
   constexpr int NI = (PB * kRG + kThreads - 1) / kThreads;  // items per thread
   extern __shared__ __align__(16) unsigned char smem[];
-  const int w = a.w;
+  const int w = W > 0 ? W : a.w;
   // blocks of 2 x 2 (x 1) bins: the first two dimensions doubled
   const int st0 = 2 * a.tile[0], st1 = 2 * a.tile[1], st2 = D > 2 ? a.tile[2] : 1;
   const int pc0 = st0 + w - 1, pc1 = st1 + w - 1, pc2 = D > 2 ? st2 + w - 1 : 1;
@@ -689,27 +691,38 @@ __global__ __launch_bounds__(kThreads) void interp_super_kernel(
           const int rg = it % RG, p = it / RG;
           const T* pr = s_rec + p * ls;
           const int o0 = s_cell[D * p], o1 = s_cell[D * p + 1], o2 = D > 2 ? s_cell[D * p + 2] : 0;
-          double acc = 0.0;
+          // beta_2g, beta_2g+1 over this item's window rows, then weighted in fp64
+          T sx = 0, sy = 0;
           // window row (q1, q2) of row index q2 w + q1, stepped by RG < w
           int q1 = D > 2 ? (rg < w ? rg : rg - w) : rg, q2 = D > 2 && rg >= w ? 1 : 0;
           for (int row = rg; row < cellsw; row += RG) {
             const V* tr = tile + ((o2 + q2) * pc1 + (o1 + q1)) * ps0 + o0;
             T rx = 0, ry = 0;
-            for (int q0 = 0; q0 < w; ++q0) {
-              const T ps = pr[q0];
-              const V gv = tr[q0];
-              rx += ps * gv.x;
-              ry += ps * gv.y;
+            if constexpr (W > 0) {
+#pragma unroll
+              for (int q0 = 0; q0 < W; ++q0) {
+                const T ps = pr[q0];
+                const V gv = tr[q0];
+                rx += ps * gv.x;
+                ry += ps * gv.y;
+              }
+            } else {
+              for (int q0 = 0; q0 < w; ++q0) {
+                const T ps = pr[q0];
+                const V gv = tr[q0];
+                rx += ps * gv.x;
+                ry += ps * gv.y;
+              }
             }
             const T wv = D > 2 ? pr[w + q1] * pr[2 * w + q2] : pr[w + row];
-            acc += (double)wv * ((double)pr[wko + 2 * g] * (double)rx +
-                                          (double)pr[wko + 2 * g + 1] * (double)ry);
+            sx += wv * rx;
+            sy += wv * ry;
             q1 += RG;
             if (D > 2) {
               while (q1 >= w) { q1 -= w; ++q2; }
             }
           }
-          part[k] += acc;
+          part[k] += (double)pr[wko + 2 * g] * (double)sx + (double)pr[wko + 2 * g + 1] * (double)sy;
         }
       }
     }
@@ -927,8 +940,14 @@ void launch_interp_super(Plan* P, const Records& R, const double* xs, double* ys
                      (P->d > 2 ? P->tile[2] + P->w - 1 : 1);
   // software-pipelined tile loads when a pair's tile fits kTE cells per thread
   const bool pipe = ucells <= (P->d > 2 ? kTE<3> : kTE<2>) * kThreads;
-  auto kern = P->d == 2 ? (pipe ? interp_super_kernel<T, true, 2> : interp_super_kernel<T, false, 2>)
-                        : (pipe ? interp_super_kernel<T, true, 3> : interp_super_kernel<T, false, 3>);
+  // compile-time window widths of the common plans (fp32 at tol 1e-4: 5 in
+  // 3-D, 7 in 2-D at the automatic oversampling; fp64 at 1e-8 in 2-D: 12)
+  auto pick = [&](auto d2, auto d3) { return P->d == 2 ? d2 : d3; };
+  auto kern = pipe ? (P->w == 5    ? pick(interp_super_kernel<T, true, 2, 5>, interp_super_kernel<T, true, 3, 5>)
+                      : P->w == 7  ? pick(interp_super_kernel<T, true, 2, 7>, interp_super_kernel<T, true, 3, 7>)
+                      : P->w == 12 ? pick(interp_super_kernel<T, true, 2, 12>, interp_super_kernel<T, true, 3, 12>)
+                                   : pick(interp_super_kernel<T, true, 2, 0>, interp_super_kernel<T, true, 3, 0>))
+                   : pick(interp_super_kernel<T, false, 2, 0>, interp_super_kernel<T, false, 3, 0>);
   if (interp_super_smem<T>(P, R.rs) > kSmemCap) allow_big_lds(kern);
   hipLaunchKernelGGL(kern, dim3((unsigned)R.n_in_work2), dim3(kThreads),
                      interp_super_smem<T>(P, R.rs), P->stream, a,
