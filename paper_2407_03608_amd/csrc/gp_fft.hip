@@ -175,8 +175,15 @@ constexpr int next_radix(int rem, int ept) {
 
 __device__ __forceinline__ int lpad(int p) { return p + (p >> 5); }
 
+// offset of element i of a sequence: (i / ip) es + (i % ip) es1, ip = 1 << ips
+__device__ __forceinline__ int64_t elem_off(int i, int ips, int64_t es, int64_t es1) {
+  return (int64_t)(i >> ips) * es + (int64_t)(i & ((1 << ips) - 1)) * es1;
+}
+
 struct KParams {
   int64_t ntrans, inner, in_os, out_os, in_es, in_cs, out_es, out_cs;
+  int64_t in_cs1, in_es1, out_cs1, out_es1;
+  int in_cps, in_ips, out_cps, out_ips;  // log2 of the interleave factors (0 or 1)
   int n_in, in_start, n_out, out_start, sign;
   int64_t L4, tw4_mod;
   int tw4_at_load;
@@ -257,7 +264,7 @@ __device__ __forceinline__ void stages(V (&v)[EPT], T* __restrict__ buf, int jt,
             if (s > 0) wv.y = -wv.y;
             val = cmul(val, wv);
           }
-          dst[(int64_t)i * dstride] = val;
+          dst[elem_off(i, p.out_ips, dstride, p.out_es1)] = val;
         }
       }
     }
@@ -293,8 +300,8 @@ __global__ __launch_bounds__(B*(L / EPT)) void fft_pass_kernel(
   const int64_t t = bid * B + b;
   const bool act = t < p.ntrans;
   const int64_t o = act ? t / p.inner : 0, c = act ? t - o * p.inner : 0;
-  const V* src = in + o * p.in_os + c * p.in_cs;
-  V* dst = out + o * p.out_os + c * p.out_cs;
+  const V* src = in + o * p.in_os + (c >> p.in_cps) * p.in_cs + (c & ((1 << p.in_cps) - 1)) * p.in_cs1;
+  V* dst = out + o * p.out_os + (c >> p.out_cps) * p.out_cs + (c & ((1 << p.out_cps) - 1)) * p.out_cs1;
   const int64_t row4 = tw4 != nullptr ? o % p.tw4_mod : 0;
   constexpr int R1 = next_radix(L, EPT);
   constexpr int NB1 = EPT / R1;
@@ -309,7 +316,7 @@ __global__ __launch_bounds__(B*(L / EPT)) void fft_pass_kernel(
       if (i < 0) i += L;
       V val = V{T(0), T(0)};
       if (act && i < p.n_in) {
-        val = src[(int64_t)i * p.in_es];
+        val = src[elem_off(i, p.in_ips, p.in_es, p.in_es1)];
         if (tw4 != nullptr && p.tw4_at_load) {
           V wv = tw4[((int64_t)pos * row4) % p.L4];
           if (p.sign > 0) wv.y = -wv.y;
@@ -346,6 +353,14 @@ void launch_len(const FftPass& q, const void* in, void* out, const void* tw, hip
   p.in_cs = q.in_cs ? q.in_cs : 1;
   p.out_es = q.out_es ? q.out_es : q.inner;
   p.out_cs = q.out_cs ? q.out_cs : 1;
+  p.in_cs1 = q.in_cs1;
+  p.in_es1 = q.in_es1;
+  p.out_cs1 = q.out_cs1;
+  p.out_es1 = q.out_es1;
+  p.in_cps = q.in_cp == 2;
+  p.in_ips = q.in_ip == 2;
+  p.out_cps = q.out_cp == 2;
+  p.out_ips = q.out_ip == 2;
   p.n_in = q.n_in;
   p.in_start = ((q.in_start % L) + L) % L;
   p.n_out = q.n_out;
@@ -379,12 +394,12 @@ void launch_len(const FftPass& q, const void* in, void* out, const void* tw, hip
                        static_cast<const V*>(tw), static_cast<const V*>(q.tw4), p);
     GP_CHECK_LAUNCH();
   } else {
-    // Long strided (column) transforms: two columns per workgroup, so pairs of
-    // adjacent lanes read adjacent elements of one cache line (fp64 6144-point
-    // columns: 1.76 -> 1.70 ms at d=2 N=1e6; one 100 KB workgroup per CU holds
-    // as many waves as two single-column ones, whose VGPRs allow two per CU).
+    // Long strided (column) fp32 transforms: two columns per workgroup, so
+    // pairs of adjacent lanes read adjacent elements of one cache line.  fp64
+    // ones stay one per workgroup (two per workgroup: 1.56 against 1.47 ms for
+    // the forward column pass at d=2 N=1e6 with contiguous output).
     if constexpr (B == 1 && L >= 6144) {
-      if (q.inner > 1) {
+      if (q.inner > 1 && sizeof(T) == 4) {
         const int64_t nb2 = (p.ntrans + 1) / 2;
         if (nb2 <= 0) return;
         hipLaunchKernelGGL((fft_pass_kernel<T, L, EPT, 2>), dim3((unsigned)nb2), dim3(2 * (L / EPT)),
@@ -443,6 +458,8 @@ void fft_pass(int fp64, const FftPass& p, const void* in, void* out, const void*
               hipStream_t s) {
   if (p.n_in > p.L || p.n_out > p.L || p.n_in < 0 || p.n_out < 0)
     throw Error{GP_EINVAL, "fft_pass: window longer than the transform"};
+  for (int f : {p.in_cp, p.in_ip, p.out_cp, p.out_ip})
+    if (f != 1 && f != 2) throw Error{GP_EINVAL, "fft_pass: interleave factor must be 1 or 2"};
   if (fp64)
     dispatch<double>(p, in, out, twiddles, s);
   else

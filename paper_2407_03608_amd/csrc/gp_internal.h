@@ -57,10 +57,13 @@ struct FftPass {
   int64_t L4 = 0;
   int tw4_at_load = 1;
   // Transform (o, c), o < n_outer, c < inner, reads element i at
-  // in + o in_os + c in_cs + i in_es and writes element i at
-  // out + o out_os + c out_cs + i out_es.  es = 0 means inner (the sequence
+  //   in + o in_os + (c / cp) in_cs + (c % cp) in_cs1 + (i / ip) in_es + (i % ip) in_es1
+  // and writes element i at the same form over out (cp, ip = 1 or 2: pairs of
+  // transforms or of elements interleaved).  es = 0 means inner (the sequence
   // runs across the batch), cs = 0 means 1.
   int64_t in_es = 0, in_cs = 0, out_es = 0, out_cs = 0;
+  int in_cp = 1, in_ip = 1, out_cp = 1, out_ip = 1;
+  int64_t in_cs1 = 0, in_es1 = 0, out_cs1 = 0, out_es1 = 0;
 };
 void fft_pass(int fp64, const FftPass& p, const void* in, void* out, const void* twiddles,
               hipStream_t s);

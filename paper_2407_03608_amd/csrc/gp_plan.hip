@@ -447,7 +447,7 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
     szC = P->fourstep ? nf : mc;
   } else if (d == 2) {
     szA = (int64_t)P->na[0] * P->na[1];
-    szB = (int64_t)P->na[1] * mc;
+    szB = (int64_t)(P->na[1] + (P->na[1] & 1)) * (mc + (mc & 1));  // pair-interleaved (see fft_all)
     szC = mc * mc;
   } else {
     szA = (int64_t)P->na[0] * P->na[1] * P->na[2];
