@@ -391,6 +391,7 @@ def run_serving(args, n_requests):
     del dev
     lat = np.array([results[k]["t_done"] - results[k]["t_submit"] for k in range(len(reqs))])
     queue = np.array([results[k]["t_start"] - results[k]["t_submit"] for k in range(len(reqs))])
+    ready = np.array([results[k]["t_ready"] - results[k]["t_start"] for k in range(len(reqs))])
     iters = np.array([results[k]["iters"] for k in range(len(reqs))])
     nonconv = int(sum(results[k]["status"] != 0 for k in range(len(reqs))))
     return {"requests": len(reqs),
@@ -401,6 +402,12 @@ def run_serving(args, n_requests):
             "p99_s": round(float(np.percentile(lat, 99)), 4),
             "max_s": round(float(lat.max()), 4),
             "mean_queue_s": round(float(queue.mean()), 4),
+            "admission_to_first_matvec_s": {"p50": round(float(np.percentile(ready, 50)), 4),
+                                            "p99": round(float(np.percentile(ready, 99)), 4),
+                                            "max": round(float(ready.max()), 4),
+                                            "what": "plan build of the request's operators, "
+                                                    "from slot admission to the first matvec "
+                                                    "queued"},
             "solves_per_s": round(len(reqs) / wall, 4),
             "wall_s": round(wall, 3),
             "peak_running": st["peak_running"],

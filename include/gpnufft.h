@@ -29,6 +29,10 @@
  *  - A plan copies what it needs at creation and keeps no reference to the
  *    caller's buffers.  One thread may use a plan at a time; distinct plans
  *    are independent and may be used concurrently on distinct streams.
+ *  - Device memory is taken and released in stream order (HIP's stream-ordered
+ *    allocator on the device's default pool, which keeps released memory for
+ *    reuse): creating and destroying plans never waits for work on other
+ *    streams.  The plan's stream must outlive the plan.
  *  - Results are deterministic: every reduction has a fixed order, so the
  *    same inputs and options give the same bits, alone or next to other work.
  */
@@ -330,6 +334,9 @@ typedef struct {
   size_t device_bytes;      /* admission bytes of the request */
   int slot;                 /* worker slot that ran it */
   int precision;            /* path it was solved on: GP_FP64 or GP_FP32_BULK */
+  double t_ready;           /* seconds since creation when its plans were built; its
+                               first matvec is queued right after (t_ready - t_start is
+                               the time from admission to the first matvec) */
 } gp_request_info;
 typedef struct {
   int64_t submitted, completed, queued;
@@ -368,7 +375,9 @@ int gp_server_destroy(gp_server_t srv);
 int gp_plan_rules(int d, double nu, double tol, double l_min, double l_max, double extent,
                   const gp_opts* opts, gp_plan_params* out);
 
-/* Change the stream later work of this plan is ordered on. */
+/* Change the stream later work of this plan is ordered on.  Waits for the
+   work queued on the old stream; the plan's device memory is afterwards
+   released in the order of the new stream (which must outlive the plan). */
 int gp_plan_set_stream(gp_plan_t plan, void* stream);
 
 int gp_plan_destroy(gp_plan_t plan);

@@ -67,7 +67,7 @@ PhaseScope::~PhaseScope() {
 Plan::~Plan() {
   // work still queued on the plan's stream may use its buffers
   if (cg_part.p || gridA.p) (void)hipStreamSynchronize(stream);
-  if (cg_hS) (void)hipHostFree(cg_hS);
+  pinned_scalars_put(cg_hS);
   for (auto& ev : events) {
     (void)hipEventDestroy(ev.a);
     (void)hipEventDestroy(ev.b);
@@ -349,8 +349,8 @@ int gp_cg_solve_multi(gp_plan_t h, int m, const double* y, double* alpha, double
     if (block != 0 && block != 1) throw Error{GP_EINVAL, "block must be 0 or 1"};
     int mb = multi_capacity(P, block ? std::min(m, 16) : m);
     DevBuf bs, xs;
-    bs.alloc((size_t)mb * n * sizeof(double));
-    xs.alloc((size_t)mb * n * sizeof(double));
+    bs.alloc((size_t)mb * n * sizeof(double), s);
+    xs.alloc((size_t)mb * n * sizeof(double), s);
     std::vector<int> it(m);
     std::vector<double> rr(m);
     int status = GP_OK;
@@ -464,11 +464,11 @@ int gp_posterior_cov(gp_plan_t h, int64_t m, const double* targets, const double
     // application shared by the block)
     const int mb = multi_capacity(P, (int)std::min<int64_t>(m, 16));
     DevBuf e, prior, cross, kb, vb;
-    e.alloc(m * sizeof(double));
-    prior.alloc((size_t)mb * m * sizeof(double));
-    cross.alloc(m * sizeof(double));
-    kb.alloc((size_t)mb * n * sizeof(double));
-    vb.alloc((size_t)mb * n * sizeof(double));
+    e.alloc(m * sizeof(double), s);
+    prior.alloc((size_t)mb * m * sizeof(double), s);
+    cross.alloc(m * sizeof(double), s);
+    kb.alloc((size_t)mb * n * sizeof(double), s);
+    vb.alloc((size_t)mb * n * sizeof(double), s);
     const unsigned mblk = (unsigned)((m + 255) / 256);
     int64_t total = 0;
     double worst = 0.0;
@@ -568,7 +568,10 @@ int gp_plan_get_timing(gp_plan_t h, gp_timing* out) {
 int gp_plan_set_stream(gp_plan_t h, void* stream) {
   return guarded([&] {
     if (!h) throw Error{GP_EINVAL, "null plan"};
+    // work queued on the old stream may still use the plan's buffers
+    GP_HIP(hipStreamSynchronize(h->P.stream));
     h->P.stream = static_cast<hipStream_t>(stream);
+    retag_plan_stream(&h->P, h->P.stream);
     return GP_OK;
   });
 }

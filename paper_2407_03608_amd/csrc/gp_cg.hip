@@ -388,11 +388,11 @@ int cg_multi_sorted(Plan* P, int m, const double* b, double* x, double tol, int 
   const int64_t n = P->n;
   hipStream_t s = P->stream;
   DevBuf rb, pb, apb, partb, Sb;
-  rb.alloc((size_t)m * n * sizeof(double));
-  pb.alloc((size_t)m * n * sizeof(double));
-  apb.alloc((size_t)m * n * sizeof(double));
-  partb.alloc((size_t)m * kRedBlocks * sizeof(double));
-  Sb.alloc((size_t)m * kCgScalars * sizeof(double));
+  rb.alloc((size_t)m * n * sizeof(double), s);
+  pb.alloc((size_t)m * n * sizeof(double), s);
+  apb.alloc((size_t)m * n * sizeof(double), s);
+  partb.alloc((size_t)m * kRedBlocks * sizeof(double), s);
+  Sb.alloc((size_t)m * kCgScalars * sizeof(double), s);
   double* r = rb.as<double>();
   double* p = pb.as<double>();
   double* Ap = apb.as<double>();
@@ -680,14 +680,14 @@ int cg_block_sorted(Plan* P, int m, const double* b, double* x, double tol, int 
   const int64_t n = P->n;
   hipStream_t s = P->stream;
   DevBuf Rb, Pb, Qb, Zb, partb, Gb, cob, colb;
-  Rb.alloc((size_t)m * n * sizeof(double));
-  Pb.alloc((size_t)m * n * sizeof(double));
-  Qb.alloc((size_t)m * n * sizeof(double));
-  Zb.alloc((size_t)m * n * sizeof(double));
-  partb.alloc((size_t)kRedBlocks * m * m * sizeof(double));
-  Gb.alloc((size_t)m * m * sizeof(double));
-  cob.alloc((size_t)2 * m * m * sizeof(double));
-  colb.alloc(kMaxBlock * sizeof(int));
+  Rb.alloc((size_t)m * n * sizeof(double), s);
+  Pb.alloc((size_t)m * n * sizeof(double), s);
+  Qb.alloc((size_t)m * n * sizeof(double), s);
+  Zb.alloc((size_t)m * n * sizeof(double), s);
+  partb.alloc((size_t)kRedBlocks * m * m * sizeof(double), s);
+  Gb.alloc((size_t)m * m * sizeof(double), s);
+  cob.alloc((size_t)2 * m * m * sizeof(double), s);
+  colb.alloc(kMaxBlock * sizeof(int), s);
   double* R = Rb.as<double>();
   double* Pm = Pb.as<double>();
   double* Q = Qb.as<double>();

@@ -27,17 +27,28 @@ void clear_error();
 #define GP_CHECK_LAUNCH() GP_HIP(hipGetLastError())
 
 // --------------------------------------------------------- device buffers --
+// Stream-ordered device memory: alloc takes memory in the order of stream st
+// (usable by work queued on st afterwards) and release returns it in the order
+// of the stream it was taken on, so neither waits for the device.  The memory
+// comes from the device's pool, which keeps released memory for reuse instead
+// of returning it to the driver.  Work on other streams that uses a buffer
+// must be complete before the buffer is released.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  hipStream_t s = nullptr;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
-  void alloc(size_t b);
+  void alloc(size_t b, hipStream_t st);
   void release();
   template <class T> T* as() const { return static_cast<T*>(p); }
 };
+// Pinned host blocks of kCgScalars doubles, kept for reuse (freeing pinned
+// memory would wait for the whole device).
+double* pinned_scalars_get();
+void pinned_scalars_put(double* h);
 
 // One batched pass of 1-D FFTs along one axis of a strided array:
 // element (o, pos, c) of the input lives at in[o*in_os + i*inner + c] where
@@ -220,6 +231,9 @@ struct NuArgs {
   int add_noise, first_chunk;
 };
 NuArgs nu_args(const Plan* P, const Records& R);
+// Release the plan's device memory in the order of stream st from now on
+// (after its previous stream has been synchronised).
+void retag_plan_stream(Plan* P, hipStream_t st);
 // Grid A (spread output, interpolation input) of the current vector set.
 void* grid_a_current(const Plan* P);
 
@@ -232,6 +246,9 @@ inline bool spread_uses_sub_tiles(const Plan* P) { return spread_sub_side(P) > 0
 size_t spread_list_bound_bytes(const Plan* P, int64_t n);
 void build_spread_lists(Plan* P, Records& R);
 void spread_sub_launch(Plan* P, const Records& R, const double* xs);
+// out[0..n) = exclusive prefix sums of the counts in[0..n) (device arrays, on
+// stream s); *total = their sum, read back to the host.
+void exclusive_scan_counts(const int* in, int64_t n, int64_t* out, hipStream_t s, int64_t* total);
 void build_records_into(Plan* P, int64_t n, const double* pts, const double* sig,
                         const double* l, Records& R, int* out_of_box);
 void gather_sorted(Plan* P, const double* x_user, double* x_sorted);

@@ -1205,10 +1205,10 @@ static void ensure_multi(Plan* P, int m) {
   if (m <= P->m_cap) return;
   const size_t cs = P->precision == GP_FP64 ? 16 : 8;
   const size_t G = (size_t)P->npair * m;
-  P->mA.alloc(G * P->grid_elems[0] * cs);
-  P->mB.alloc(G * P->grid_elems[1] * cs);
-  if (P->grid_elems[2]) P->mB2.alloc(G * P->grid_elems[2] * cs);
-  P->mC.alloc(G * P->grid_elems[3] * cs);
+  P->mA.alloc(G * P->grid_elems[0] * cs, P->stream);
+  P->mB.alloc(G * P->grid_elems[1] * cs, P->stream);
+  if (P->grid_elems[2]) P->mB2.alloc(G * P->grid_elems[2] * cs, P->stream);
+  P->mC.alloc(G * P->grid_elems[3] * cs, P->stream);
   // the 1-D four-step keeps zeros in A outside the active box (see fft_all)
   if (P->fourstep) GP_HIP(hipMemsetAsync(P->mA.p, 0, P->mA.bytes, P->stream));
   P->m_cap = m;
@@ -1252,7 +1252,7 @@ void posterior_sorted(Plan* P, const double* xs, int64_t m, const double* tpts,
   build_records_into(P, m, tpts, tsig, tl, T, &oob);
   if (oob) throw Error{GP_ERANGE, "posterior target outside the plan's box"};
   DevBuf tmp;
-  tmp.alloc(m * sizeof(double));
+  tmp.alloc(m * sizeof(double), P->stream);
   if (P->precision == GP_FP64) {
     forward_and_mix<double>(P, P->rec, xs);
     interp_dispatch<double>(P, T, nullptr, tmp.as<double>(), 0);

@@ -10,28 +10,103 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <mutex>
+
+#include <climits>
 
 #include "gp_internal.h"
 
 namespace gp {
 
-void DevBuf::alloc(size_t b) {
+namespace {
+std::mutex& pinned_mu() {
+  static std::mutex m;
+  return m;
+}
+std::vector<double*>& pinned_free() {
+  static std::vector<double*> v;  // held until the process ends
+  return v;
+}
+
+// Once per device: keep released pool memory cached (the default threshold
+// would hand it back to the driver at the next synchronisation).
+hipMemPool_t device_pool() {
+  static std::mutex mu;
+  static std::vector<std::pair<int, hipMemPool_t>> pools;
+  int dev = 0;
+  GP_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  for (auto& q : pools)
+    if (q.first == dev) return q.second;
+  hipMemPool_t pool = nullptr;
+  GP_HIP(hipDeviceGetDefaultMemPool(&pool, dev));
+  uint64_t keep = UINT64_MAX;
+  GP_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
+  pools.push_back({dev, pool});
+  return pool;
+}
+}  // namespace
+
+void DevBuf::alloc(size_t b, hipStream_t st) {
   release();
   if (b == 0) b = 256;
-  hipError_t e = hipMalloc(&p, b);
+  hipMemPool_t pool = device_pool();
+  hipError_t e = hipMallocAsync(&p, b, st);
+  if (e != hipSuccess) {
+    // hand the pool's cached memory back and try once more
+    (void)hipGetLastError();
+    (void)hipDeviceSynchronize();
+    (void)hipMemPoolTrimTo(pool, 0);
+    e = hipMallocAsync(&p, b, st);
+  }
   if (e != hipSuccess) {
     p = nullptr;
     (void)hipGetLastError();
-    throw Error{GP_ENOMEM, "hipMalloc(" + std::to_string(b) + " bytes) failed: " +
+    throw Error{GP_ENOMEM, "device allocation of " + std::to_string(b) + " bytes failed: " +
                                hipGetErrorString(e)};
   }
   bytes = b;
+  s = st;
 }
 
 void DevBuf::release() {
-  if (p) (void)hipFree(p);
+  if (p) (void)hipFreeAsync(p, s);
   p = nullptr;
   bytes = 0;
+  s = nullptr;
+}
+
+void retag_plan_stream(Plan* P, hipStream_t st) {
+  Records& R = P->rec;
+  DevBuf* bufs[] = {&R.perm, &R.cell, &R.pw, &R.bin_start, &R.sp_work, &R.sp_red, &R.in_work,
+                    &R.in_work2, &R.part, &R.sub_off, &R.sub_list, &P->nodes_d, &P->bary_d,
+                    &P->gtab, &P->etab, &P->vtd, &P->lr_off, &P->atab, &P->rowidx, &P->dec,
+                    &P->tw[0], &P->tw[1], &P->tw[2], &P->tw4, &P->gridA, &P->gridB, &P->gridB2,
+                    &P->gridC, &P->mA, &P->mB, &P->mB2, &P->mC, &P->vec, &P->cg_part, &P->cg_S};
+  for (DevBuf* b : bufs)
+    if (b->p) b->s = st;
+}
+
+double* pinned_scalars_get() {
+  static_assert(kCgScalars > 0, "");
+  {
+    std::lock_guard<std::mutex> lk(pinned_mu());
+    auto& fl = pinned_free();
+    if (!fl.empty()) {
+      double* h = fl.back();
+      fl.pop_back();
+      return h;
+    }
+  }
+  double* h = nullptr;
+  GP_HIP(hipHostMalloc((void**)&h, kCgScalars * sizeof(double), hipHostMallocDefault));
+  return h;
+}
+
+void pinned_scalars_put(double* h) {
+  if (!h) return;
+  std::lock_guard<std::mutex> lk(pinned_mu());
+  pinned_free().push_back(h);
 }
 
 namespace {
@@ -76,6 +151,84 @@ __global__ void records_kernel(RecArgs a, const double* __restrict__ pts,
   sp_tmp[i] = lp * 0.70710678118654752440;
   pf_tmp[i] = sig[i] * pow(2.0 / (3.14159265358979323846 * lp * lp), 0.25 * a.d);
   bin_of[i] = (int)bin;
+}
+
+// ------------------------------------------------------------ bin sort ----
+// Stable sort of the points by bin on the device, the order of a counting
+// sort: by bin, and inside a bin by caller index.  The points are cut into
+// chunks of consecutive indices; cnt[bin][chunk] counts them, its exclusive
+// scan in bin-major order gives each (bin, chunk) its first sorted position,
+// and one workgroup per chunk walks its points in batches of kSortBatch,
+// sorts each batch by (bin, index) in LDS and places every run of equal bins
+// after what earlier batches of the chunk placed there.
+constexpr int kSortBatch = 256;
+
+__global__ __launch_bounds__(kSortBatch) void sort_count_kernel(int64_t n, int64_t chunk, int64_t nch,
+                                                                const int* __restrict__ bin_of,
+                                                                int* __restrict__ cnt) {
+  const int64_t i = (int64_t)blockIdx.x * kSortBatch + threadIdx.x;
+  if (i >= n) return;
+  atomicAdd(&cnt[(int64_t)bin_of[i] * nch + i / chunk], 1);
+}
+
+__global__ void bin_start_kernel(int64_t nbins, int64_t nch, int64_t n, const int64_t* __restrict__ off,
+                                 int* __restrict__ bin_start) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < nbins) bin_start[b] = (int)off[b * nch];
+  if (b == nbins) bin_start[b] = (int)n;
+}
+
+__global__ __launch_bounds__(kSortBatch) void sort_place_kernel(int64_t n, int64_t chunk, int64_t nch,
+                                                                const int* __restrict__ bin_of,
+                                                                unsigned long long* __restrict__ off,
+                                                                int* __restrict__ pos_of) {
+  __shared__ int s_key[kSortBatch], s_idx[kSortBatch], s_gs[kSortBatch];
+  __shared__ unsigned long long s_base[kSortBatch];
+  const int t = threadIdx.x;
+  const int64_t c = blockIdx.x;
+  const int64_t lo = c * chunk, hi = min(n, lo + chunk);
+  for (int64_t base = lo; base < hi; base += kSortBatch) {
+    const int64_t i = base + t;
+    __syncthreads();
+    s_key[t] = i < hi ? bin_of[i] : INT_MAX;
+    s_idx[t] = (int)(i - lo);  // unique within the chunk
+    __syncthreads();
+    // bitonic sort by (key, index), ascending
+    for (int k = 2; k <= kSortBatch; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        const int u = t ^ j;
+        if (u > t) {
+          const bool up = (t & k) == 0;
+          const int ka = s_key[t], kb = s_key[u], ia = s_idx[t], ib = s_idx[u];
+          const bool gt = ka > kb || (ka == kb && ia > ib);
+          if (gt == up) {
+            s_key[t] = kb;
+            s_key[u] = ka;
+            s_idx[t] = ib;
+            s_idx[u] = ia;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    // first position of each run of equal keys (inclusive max-scan of heads)
+    const int key = s_key[t];
+    const bool head = t == 0 || s_key[t - 1] != key;
+    s_gs[t] = head ? t : 0;
+    __syncthreads();
+    for (int d = 1; d < kSortBatch; d <<= 1) {
+      const int v = t >= d ? s_gs[t - d] : 0;
+      __syncthreads();
+      s_gs[t] = max(s_gs[t], v);
+      __syncthreads();
+    }
+    const int gs = s_gs[t];
+    const bool tail = t == kSortBatch - 1 || s_key[t + 1] != key;
+    if (tail && key != INT_MAX)
+      s_base[gs] = atomicAdd(&off[(int64_t)key * nch + c], (unsigned long long)(t - gs + 1));
+    __syncthreads();
+    if (key != INT_MAX) pos_of[lo + s_idx[t]] = (int)(s_base[gs] + (unsigned long long)(t - gs));
+  }
 }
 
 // Scatter the per-point data into bin order and evaluate, once per plan, the
@@ -285,23 +438,23 @@ static void build_work_lists(Plan* P, Records& R, const std::vector<int>& start,
   hipStream_t s = P->stream;
   R.n_in_work2 = (int64_t)inw2.size() / 4;
   if (!inw2.empty()) {
-    R.in_work2.alloc(inw2.size() * sizeof(int));
+    R.in_work2.alloc(inw2.size() * sizeof(int), P->stream);
     GP_HIP(hipMemcpyAsync(R.in_work2.p, inw2.data(), inw2.size() * sizeof(int), hipMemcpyHostToDevice, s));
   }
   R.n_sp_work = (int64_t)spw.size() / 4;
   R.n_sp_red = (int64_t)spr.size() / 4;
   R.n_in_work = (int64_t)inw.size() / 4;
   R.n_slots = slots;
-  R.sp_work.alloc(spw.size() * sizeof(int));
+  R.sp_work.alloc(spw.size() * sizeof(int), P->stream);
   GP_HIP(hipMemcpyAsync(R.sp_work.p, spw.data(), spw.size() * sizeof(int), hipMemcpyHostToDevice, s));
   if (!spr.empty()) {
-    R.sp_red.alloc(spr.size() * sizeof(int));
+    R.sp_red.alloc(spr.size() * sizeof(int), P->stream);
     GP_HIP(hipMemcpyAsync(R.sp_red.p, spr.data(), spr.size() * sizeof(int), hipMemcpyHostToDevice, s));
     const int64_t tcells = (int64_t)P->tile[0] * P->tile[1] * P->tile[2];
-    R.part.alloc((size_t)slots * tcells * slot_pairs(P) * cs);
+    R.part.alloc((size_t)slots * tcells * slot_pairs(P) * cs, P->stream);
   }
   if (!inw.empty()) {
-    R.in_work.alloc(inw.size() * sizeof(int));
+    R.in_work.alloc(inw.size() * sizeof(int), P->stream);
     GP_HIP(hipMemcpyAsync(R.in_work.p, inw.data(), inw.size() * sizeof(int), hipMemcpyHostToDevice, s));
   }
   // the host vectors are released when this returns: wait for the copies
@@ -328,13 +481,13 @@ void build_records_into(Plan* P, int64_t n, const double* pts, const double* sig
   a.w = P->w;
   const size_t tsz = P->precision == GP_FP64 ? sizeof(double) : sizeof(float);
   DevBuf bin_of, posd, cell_tmp, frac_tmp, sp_tmp, pf_tmp, bad;
-  bin_of.alloc(n * sizeof(int));
-  posd.alloc(n * sizeof(int));
-  cell_tmp.alloc(n * d * sizeof(int));
-  frac_tmp.alloc(n * d * sizeof(double));
-  sp_tmp.alloc(n * sizeof(double));
-  pf_tmp.alloc(n * sizeof(double));
-  bad.alloc(sizeof(int));
+  bin_of.alloc(n * sizeof(int), P->stream);
+  posd.alloc(n * sizeof(int), P->stream);
+  cell_tmp.alloc(n * d * sizeof(int), P->stream);
+  frac_tmp.alloc(n * d * sizeof(double), P->stream);
+  sp_tmp.alloc(n * sizeof(double), P->stream);
+  pf_tmp.alloc(n * sizeof(double), P->stream);
+  bad.alloc(sizeof(int), P->stream);
   GP_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
   const int bs = 256;
   const unsigned nb = (unsigned)((n + bs - 1) / bs);
@@ -342,28 +495,45 @@ void build_records_into(Plan* P, int64_t n, const double* pts, const double* sig
                      cell_tmp.as<int>(), frac_tmp.as<double>(), sp_tmp.as<double>(),
                      pf_tmp.as<double>(), bad.as<int>());
   GP_CHECK_LAUNCH();
-  // Stable counting sort by tile on the host (plan time): points keep their
-  // caller order inside a tile, so every plan of the same input is identical.
-  std::vector<int> hb(n);
-  int hbad = 0;
-  GP_HIP(hipMemcpyAsync(hb.data(), bin_of.p, n * sizeof(int), hipMemcpyDeviceToHost, s));
-  GP_HIP(hipMemcpyAsync(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
-  GP_HIP(hipStreamSynchronize(s));
-  if (out_of_box) *out_of_box = hbad;
-  std::vector<int> start(P->n_bins + 1, 0);
-  for (int64_t i = 0; i < n; ++i) start[hb[i] + 1] += 1;
-  for (int64_t b = 0; b < P->n_bins; ++b) start[b + 1] += start[b];
-  std::vector<int> fill(start.begin(), start.end() - 1), hpos(n);
-  for (int64_t i = 0; i < n; ++i) hpos[i] = fill[hb[i]]++;
+  // Stable sort by tile on the device: points keep their caller order inside
+  // a tile, so every plan of the same input is identical.  The count matrix
+  // has at most kSortCells entries (chunks of at least 1024 points).
+  constexpr int64_t kSortCells = (int64_t)1 << 22;
+  const int64_t nbins = P->n_bins;
+  const int64_t nch = std::max<int64_t>(1, std::min<int64_t>((n + 1023) / 1024, kSortCells / nbins));
+  const int64_t chunk = (n + nch - 1) / nch;
   R.n = n;
   R.rs = d * P->w + P->nkp;
-  R.perm.alloc(n * sizeof(int));
-  R.cell.alloc(n * d * sizeof(int));
-  R.pw.alloc((size_t)n * R.rs * tsz);
-  R.bin_start.alloc((P->n_bins + 1) * sizeof(int));
-  GP_HIP(hipMemcpyAsync(R.bin_start.p, start.data(), (P->n_bins + 1) * sizeof(int),
-                        hipMemcpyHostToDevice, s));
-  GP_HIP(hipMemcpyAsync(posd.p, hpos.data(), n * sizeof(int), hipMemcpyHostToDevice, s));
+  R.perm.alloc(n * sizeof(int), P->stream);
+  R.cell.alloc(n * d * sizeof(int), P->stream);
+  R.pw.alloc((size_t)n * R.rs * tsz, P->stream);
+  R.bin_start.alloc((P->n_bins + 1) * sizeof(int), P->stream);
+  {
+    DevBuf cnt, off;
+    cnt.alloc((size_t)(nbins * nch) * sizeof(int), P->stream);
+    off.alloc((size_t)(nbins * nch + 1) * sizeof(int64_t), P->stream);
+    GP_HIP(hipMemsetAsync(cnt.p, 0, cnt.bytes, s));
+    hipLaunchKernelGGL(sort_count_kernel, dim3((unsigned)((n + kSortBatch - 1) / kSortBatch)),
+                       dim3(kSortBatch), 0, s, n, chunk, nch, bin_of.as<int>(), cnt.as<int>());
+    GP_CHECK_LAUNCH();
+    int64_t total = 0;
+    exclusive_scan_counts(cnt.as<int>(), nbins * nch, off.as<int64_t>(), s, &total);
+    if (total != n) throw Error{GP_EDEVICE, "internal: bin counts do not add up"};
+    hipLaunchKernelGGL(bin_start_kernel, dim3((unsigned)((nbins + 1 + 255) / 256)), dim3(256), 0, s,
+                       nbins, nch, n, off.as<int64_t>(), R.bin_start.as<int>());
+    GP_CHECK_LAUNCH();
+    hipLaunchKernelGGL(sort_place_kernel, dim3((unsigned)nch), dim3(kSortBatch), 0, s, n, chunk, nch,
+                       bin_of.as<int>(), off.as<unsigned long long>(), posd.as<int>());
+    GP_CHECK_LAUNCH();
+    GP_HIP(hipStreamSynchronize(s));  // cnt and off are released here
+  }
+  int hbad = 0;
+  std::vector<int> start(P->n_bins + 1, 0);
+  GP_HIP(hipMemcpyAsync(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  GP_HIP(hipMemcpyAsync(start.data(), R.bin_start.p, (P->n_bins + 1) * sizeof(int),
+                        hipMemcpyDeviceToHost, s));
+  GP_HIP(hipStreamSynchronize(s));
+  if (out_of_box) *out_of_box = hbad;
   build_work_lists(P, R, start, P->precision == GP_FP64 ? 16 : 8);
 #define GP_SCATTER(T)                                                                            \
   hipLaunchKernelGGL(scatter_records_kernel<T>, dim3(nb), dim3(bs), 0, s, d, n, P->w, P->beta, \
@@ -482,12 +652,12 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
 
   auto upload = [&](DevBuf& buf, const std::vector<double>& v) {
     if (P->precision == GP_FP64) {
-      buf.alloc(v.size() * sizeof(double));
+      buf.alloc(v.size() * sizeof(double), P->stream);
       GP_HIP(hipMemcpyAsync(buf.p, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice, s));
       GP_HIP(hipStreamSynchronize(s));
     } else {
       std::vector<float> f(v.begin(), v.end());
-      buf.alloc(f.size() * sizeof(float));
+      buf.alloc(f.size() * sizeof(float), P->stream);
       GP_HIP(hipMemcpyAsync(buf.p, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice, s));
       GP_HIP(hipStreamSynchronize(s));
     }
@@ -501,7 +671,7 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
     const std::vector<double>& cst = tb.tcst;
     DevBuf dsv, dtau, dcst, dvt;
     auto up64 = [&](DevBuf& b, const std::vector<double>& v) {
-      b.alloc(v.size() * sizeof(double));
+      b.alloc(v.size() * sizeof(double), P->stream);
       GP_HIP(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice, s));
     };
     up64(dsv, svals);
@@ -512,7 +682,7 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
     const int64_t tot = P->a_rows * npk;
     const unsigned nb = (unsigned)((tot + 255) / 256);
     if (P->step3 == 0) {
-      P->atab.alloc((size_t)tot * ts);
+      P->atab.alloc((size_t)tot * ts, P->stream);
       if (P->precision == GP_FP64)
         hipLaunchKernelGGL(atab_kernel<double>, dim3(nb), dim3(256), 0, s, P->a_rows, npk, P->nkp,
                            P->nk, P->nt_eff, dsv.as<double>(), dtau.as<double>(), dcst.as<double>(),
@@ -527,7 +697,7 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
       // on the host row by row as A ~ R' R by pivoted Cholesky, keeping the
       // factors whose pivots exceed tol/100 of the row's largest diagonal
       DevBuf full;
-      full.alloc((size_t)tot * sizeof(double));
+      full.alloc((size_t)tot * sizeof(double), P->stream);
       hipLaunchKernelGGL(atab_kernel<double>, dim3(nb), dim3(256), 0, s, P->a_rows, npk, P->nkp,
                          P->nk, P->nt_eff, dsv.as<double>(), dtau.as<double>(), dcst.as<double>(),
                          dvt.as<double>(), full.as<double>());
@@ -539,12 +709,12 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
       std::vector<double> rows;
       lowrank_rows(P->a_rows, P->nk, P->nkp, hA, 1e-2 * tol, off, rows, &P->lr_rank_max,
                    &P->lr_rank_mean);
-      P->lr_off.alloc(off.size() * sizeof(int64_t));
+      P->lr_off.alloc(off.size() * sizeof(int64_t), P->stream);
       GP_HIP(hipMemcpyAsync(P->lr_off.p, off.data(), off.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
       upload(P->atab, rows);
     }
     if (d > 1) {
-      P->rowidx.alloc(rowmap.size() * sizeof(int));
+      P->rowidx.alloc(rowmap.size() * sizeof(int), P->stream);
       GP_HIP(hipMemcpyAsync(P->rowidx.p, rowmap.data(), rowmap.size() * sizeof(int),
                             hipMemcpyHostToDevice, s));
     }
@@ -552,8 +722,8 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
   }
   upload(P->vtd, tvt);
   upload(P->dec, tb.dec);
-  P->nodes_d.alloc(P->nk * sizeof(double));
-  P->bary_d.alloc(P->nk * sizeof(double));
+  P->nodes_d.alloc(P->nk * sizeof(double), P->stream);
+  P->bary_d.alloc(P->nk * sizeof(double), P->stream);
   GP_HIP(hipMemcpyAsync(P->nodes_d.p, P->sig_nodes.data(), P->nk * sizeof(double), hipMemcpyHostToDevice, s));
   GP_HIP(hipMemcpyAsync(P->bary_d.p, P->bary.data(), P->nk * sizeof(double), hipMemcpyHostToDevice, s));
 
@@ -578,10 +748,10 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
   build_spread_lists(P, P->rec);
 
   // ---- grids and vectors
-  P->gridA.alloc((size_t)G * szA * cs);
-  P->gridB.alloc((size_t)G * szB * cs);
-  if (szB2) P->gridB2.alloc((size_t)G * szB2 * cs);
-  P->gridC.alloc((size_t)G * szC * cs);
+  P->gridA.alloc((size_t)G * szA * cs, P->stream);
+  P->gridB.alloc((size_t)G * szB * cs, P->stream);
+  if (szB2) P->gridB2.alloc((size_t)G * szB2 * cs, P->stream);
+  P->gridC.alloc((size_t)G * szC * cs, P->stream);
   if (P->fourstep) GP_HIP(hipMemsetAsync(P->gridA.p, 0, P->gridA.bytes, s));
   P->grid_elems[0] = szA;
   P->grid_elems[1] = szB;
@@ -593,10 +763,10 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
   P->gv.C = P->gridC.p;
   P->gv.nsets = 1;
   P->gv.cur = 0;
-  P->vec.alloc((size_t)n * 8 * sizeof(double));
-  P->cg_part.alloc(kCgBlocks * sizeof(double));
-  P->cg_S.alloc(kCgScalars * sizeof(double));
-  GP_HIP(hipHostMalloc((void**)&P->cg_hS, kCgScalars * sizeof(double), hipHostMallocDefault));
+  P->vec.alloc((size_t)n * 8 * sizeof(double), P->stream);
+  P->cg_part.alloc(kCgBlocks * sizeof(double), P->stream);
+  P->cg_S.alloc(kCgScalars * sizeof(double), P->stream);
+  P->cg_hS = pinned_scalars_get();
   GP_HIP(hipStreamSynchronize(s));
   return GP_OK;
 }

@@ -28,7 +28,7 @@ struct SRequest {
   double* alpha = nullptr;
   double nu = 0, eta = 0;
   size_t bytes = 0;
-  double t_submit = 0, t_start = -1, t_done = -1;
+  double t_submit = 0, t_start = -1, t_ready = -1, t_done = -1;
   int status = GP_OK, iters = 0, refinements = 0, slot = -1, precision = GP_FP64;
   double rel_res = 0;
   bool done = false;
@@ -94,6 +94,7 @@ void run_request(Server& S, SRequest& r, hipStream_t st) {
   Plan P64;
   build_plan(r.d, r.n, r.pts, r.sigma, r.l, r.nu, r.eta, S.o.plan_tol, &o, &P64, false, nullptr);
   if (r.precision == GP_FP64) {
+    r.t_ready = S.now();
     double* V = P64.vec.as<double>();
     gather_sorted(&P64, r.y, V + 6 * r.n);
     GP_HIP(hipMemsetAsync(V + 2 * r.n, 0, r.n * sizeof(double), st));
@@ -112,6 +113,7 @@ void run_request(Server& S, SRequest& r, hipStream_t st) {
   o.M = P64.M;
   Plan P32;
   build_plan(r.d, r.n, r.pts, r.sigma, r.l, r.nu, r.eta, S.o.plan_tol_bulk, &o, &P32, false, nullptr);
+  r.t_ready = S.now();
   int it = 0, passes = 0;
   double rel = 0;
   r.status = cg_refined_user(&P32, &P64, r.y, r.alpha, S.o.cg_tol, S.o.inner_tol, S.o.max_iter,
@@ -315,6 +317,7 @@ static void fill_info(const SRequest& r, gp_request_info* info) {
   info->t_submit = r.t_submit;
   info->t_start = r.t_start;
   info->t_done = r.t_done;
+  info->t_ready = r.t_ready;
   info->device_bytes = r.bytes;
   info->slot = r.slot;
   info->precision = r.precision;

@@ -292,14 +292,14 @@ template <typename In>
 void exclusive_scan(const In* in, int64_t n, int64_t* out, hipStream_t s, int64_t* total) {
   const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
   DevBuf sums, soff;
-  sums.alloc((size_t)std::max<int64_t>(nb, 1) * sizeof(int64_t));
+  sums.alloc((size_t)std::max<int64_t>(nb, 1) * sizeof(int64_t), s);
   if (n > 0) {
     hipLaunchKernelGGL((scan_block_kernel<In>), dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n,
                        out, sums.as<int64_t>());
     GP_CHECK_LAUNCH();
   }
   if (nb > 1) {
-    soff.alloc((size_t)nb * sizeof(int64_t));
+    soff.alloc((size_t)nb * sizeof(int64_t), s);
     int64_t sub_total = 0;
     exclusive_scan<int64_t>(sums.as<int64_t>(), nb, soff.as<int64_t>(), s, &sub_total);
     hipLaunchKernelGGL(scan_add_kernel, dim3((unsigned)((n + kScanThreads - 1) / kScanThreads)),
@@ -408,8 +408,8 @@ void build_spread_lists(Plan* P, Records& R) {
   for (int r = 0; r < P->d; ++r) nsrc_tot *= P->nsrc;
   const size_t smem = (2 * (size_t)nsrc_tot + 1) * sizeof(int);
   DevBuf cnt;
-  cnt.alloc((size_t)nsub * sizeof(int));
-  R.sub_off.alloc((size_t)(nsub + 1) * sizeof(int64_t));
+  cnt.alloc((size_t)nsub * sizeof(int), P->stream);
+  R.sub_off.alloc((size_t)(nsub + 1) * sizeof(int64_t), P->stream);
   if (P->d == 2)
     hipLaunchKernelGGL((spread_list_build_kernel<2, false>), dim3((unsigned)nsub), dim3(kSubThreads), smem,
                        s, a, st, R.cell.as<int>(), R.bin_start.as<int>(), cnt.as<int>(), nullptr, nullptr);
@@ -422,7 +422,7 @@ void build_spread_lists(Plan* P, Records& R) {
   GP_HIP(hipMemcpyAsync(R.sub_off.as<int64_t>() + nsub, &total, sizeof(int64_t), hipMemcpyHostToDevice, s));
   const size_t bound = spread_list_bound_bytes(P, R.n);
   if ((size_t)total * sizeof(int2) > bound) throw Error{GP_EDEVICE, "internal: sub-tile lists over their bound"};
-  R.sub_list.alloc((size_t)std::max<int64_t>(total, 1) * sizeof(int2));
+  R.sub_list.alloc((size_t)std::max<int64_t>(total, 1) * sizeof(int2), P->stream);
   if (P->d == 2)
     hipLaunchKernelGGL((spread_list_build_kernel<2, true>), dim3((unsigned)nsub), dim3(kSubThreads), smem,
                        s, a, st, R.cell.as<int>(), R.bin_start.as<int>(), nullptr,
@@ -435,6 +435,10 @@ void build_spread_lists(Plan* P, Records& R) {
   GP_HIP(hipStreamSynchronize(s));  // &total is a host stack value
   R.n_sub = nsub;
   R.sub_st = st;
+}
+
+void exclusive_scan_counts(const int* in, int64_t n, int64_t* out, hipStream_t s, int64_t* total) {
+  exclusive_scan<int>(in, n, out, s, total);
 }
 
 void spread_sub_launch(Plan* P, const Records& R, const double* xs) {

@@ -171,6 +171,7 @@ class GpRequestInfo(ctypes.Structure):
         ("device_bytes", _c_sz),
         ("slot", _c_i),
         ("precision", _c_i),
+        ("t_ready", _c_d),
     ]
 
 
