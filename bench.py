@@ -139,7 +139,8 @@ def time_path(gp, torch, P, y, steps, warmup):
     return (t1 - t0), tm
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "matern_2d_hbm_counters.md")
+TRAFFIC_FILES = {"matern_2d": os.path.join(ROOT, "profiles", "matern_2d_hbm_counters.md"),
+                 "matern_3d": os.path.join(ROOT, "profiles", "matern_3d_hbm_counters.md")}
 
 
 def kernel_sources_sha256() -> str:
@@ -154,11 +155,12 @@ def kernel_sources_sha256() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(precision: str, kernel: str):
-    """HBM bytes per matvec of `kernel` from the committed counter summary, or
-    None when there is none or it was taken on other kernel sources."""
+def measured_traffic(workload: str, precision: str, kernel: str):
+    """HBM bytes per matvec of `kernel` from the committed counter summary of
+    the workload, or None when there is none or it was taken on other kernel
+    sources."""
     try:
-        txt = open(TRAFFIC_FILE).read()
+        txt = open(TRAFFIC_FILES[workload]).read()
         blk = txt.split("```json", 1)[1].split("```", 1)[0]
         data = json.loads(blk)
     except (OSError, IndexError, ValueError):
@@ -181,7 +183,9 @@ def roofline(info, tm, steps):
     b = alg_bytes(info, name)
     achieved = b / (ms * 1e-3) / 1e9
     prec = "fp64" if info["precision"] == 0 else "fp32"
-    tr = measured_traffic(prec, name) if info["d"] == 2 and info["n"] == 1_000_000 else None
+    wl = ("matern_2d" if info["d"] == 2 and info["n"] == 1_000_000 else
+          "matern_3d" if info["d"] == 3 and info["n"] == 10_000_000 else None)
+    tr = measured_traffic(wl, prec, name) if wl else None
     return {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None if tr is None else round(tr / 1e9, 4), "traffic_unit": "GB per launch group",
