@@ -276,6 +276,7 @@ __global__ void scatter_records_kernel(int d, int64_t n, int w, double beta, int
     if (k < nk) v = hit >= 0 ? (k == hit ? 1.0 : 0.0) : bary[k] / (sp - nodes[k]) / den;
     row[d * w + k] = (T)(pf * v);
   }
+  for (int c = d * w + nkp; c < rs; ++c) row[c] = T(0);  // alignment padding
 }
 
 // Row r of the precomputed step-3 tensor (rem:step3) at |n|^2 = svals[r]:
@@ -503,7 +504,10 @@ void build_records_into(Plan* P, int64_t n, const double* pts, const double* sig
   const int64_t nch = std::max<int64_t>(1, std::min<int64_t>((n + 1023) / 1024, kSortCells / nbins));
   const int64_t chunk = (n + nch - 1) / nch;
   R.n = n;
+  // rows of 2-D plans that spread on sub-tiles are padded to 16 bytes (fp32:
+  // 4 values), so the spreading kernel reads them as 16-byte vectors
   R.rs = d * P->w + P->nkp;
+  if (d == 2 && spread_uses_sub_tiles(P)) R.rs = (R.rs + 3) / 4 * 4;
   R.perm.alloc(n * sizeof(int), P->stream);
   R.cell.alloc(n * d * sizeof(int), P->stream);
   R.pw.alloc((size_t)n * R.rs * tsz, P->stream);
@@ -628,7 +632,7 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
   const int64_t G = P->npair;
   size_t bytes = 0;
   bytes += (size_t)G * (szA + szB + szB2 + szC) * cs;
-  bytes += (size_t)n * (sizeof(int) * (1 + d) + ts * (d * P->w + P->nk + 1));
+  bytes += (size_t)n * (sizeof(int) * (1 + d) + ts * (d * P->w + P->nk + 1 + 3));
   bytes += (size_t)(P->n_bins + 1) * sizeof(int);
   bytes += work_list_bound_bytes(P, n, cs);
   bytes += spread_list_bound_bytes(P, n);

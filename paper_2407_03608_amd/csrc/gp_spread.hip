@@ -137,8 +137,12 @@ __global__ __launch_bounds__(kSubThreads) void spread_list_build_kernel(
 // 2 GC weights w_k (16-byte aligned, read as vectors).  A lane adds
 // ((psi_0 x) psi_1) psi_2 w_k to its cell for every staged point, four points
 // per step (the batch is padded to a multiple of four with zero entries).
-// kStageChunk staging loads per lane are issued before their stores (4
-// measured best: d=3 N=1e7 3.23 ms against 3.32 for 8 and 6.40 for 16).
+// In 2-D (latency-bound: about 17 points per sub-tile) the point rows are read
+// as 16-byte vectors, kStageVec per lane in flight, and each value is put in
+// its slot (0.27 -> 0.24 ms at d=2 N=1e6); in 3-D (bound by VALU issue) each
+// lane fetches the slot values it stores, kStageChunk loads in flight (the
+// vector form measured 3.65 against 3.19 ms at d=3 N=1e7).
+constexpr int kStageVec = 8;
 constexpr int kStageChunk = 4;
 template <typename T, int D, int ST, int GC>
 __global__ __launch_bounds__(kSubThreads) void spread_list_kernel(
@@ -152,6 +156,8 @@ __global__ __launch_bounds__(kSubThreads) void spread_list_kernel(
   constexpr int NG = 2 * GC;
   __shared__ __align__(16) T s_v[kSubThreads * SS];
   __shared__ int s_cw[kSubThreads], s_map[kSubThreads];
+  __shared__ T s_x[kSubThreads];
+  static_assert(sizeof(T) == 4, "sub-tile spreading reads fp32 rows as 16-byte vectors");
 
   const int64_t blk = xcd_grouped(blockIdx.x, grp);
   if (blk >= nsub) return;
@@ -170,62 +176,116 @@ __global__ __launch_bounds__(kSubThreads) void spread_list_kernel(
   for (int64_t base = lo; base < hi; base += kSubThreads) {
     const int np = (int)min((int64_t)kSubThreads, hi - base);
     const int np4 = (np + 3) & ~3;
-    __syncthreads();
-    if (t < np) {
-      const int2 ent = list[base + t];
-      s_map[t] = ent.x;
-      s_cw[t] = ent.y;
-    }
-    __syncthreads();
-    // x of the lane's own point, loaded with the staging loads
-    T xv = T(0);
-    if (t < np) xv = (T)x[s_map[t]];
-    // Items per lane: NW window items (e = p NW + r ST + l, e = t + 64 k) then
-    // NG weight items (e = p NG + c, e = t + 64 (k - NW)).  Offsets into pw
-    // are 32-bit (point sets whose rows exceed 4 GiB spread whole tiles).
-#pragma unroll 1
-    for (int k0 = 0; k0 < NW + NG; k0 += kStageChunk) {
-      T vals[kStageChunk];
-      int dst[kStageChunk];
+    if constexpr (D == 2) {
+      __syncthreads();
+      if (t < np) {
+        const int2 ent = list[base + t];
+        s_map[t] = ent.x;
+        s_cw[t] = ent.y;
+        s_x[t] = (T)x[ent.x];
+      }
+      // window slots the point's window does not reach stay zero; padding
+      // entries (np .. np4) are zero throughout
+      for (int e = t; e < np * NW; e += kSubThreads) s_v[(e / NW) * SS + e % NW] = T(0);
+      for (int e = np * SS + t; e < np4 * SS; e += kSubThreads) s_v[e] = T(0);
+      __syncthreads();
+      // the rows as 16-byte vectors (rows are padded to a multiple of 4
+      // values), kStageVec per lane issued together; each value goes to the slot
+      // of the sub-tile cell it weights (dimension 0 times x_i) or, for the
+      // chunk's weights, to its place after the window slots
+      const int R4 = rs / 4, nv = np * R4;
+      const float4* __restrict__ pw4 = reinterpret_cast<const float4*>(pw);
+      for (int e0 = 0; e0 < nv; e0 += kSubThreads * kStageVec) {
+        float4 v[kStageVec];
 #pragma unroll
-      for (int j = 0; j < kStageChunk; ++j) {
-        const int k = k0 + j;
-        vals[j] = T(0);
-        dst[j] = -1;
-        if (k < NW) {
-          const int e = t + kSubThreads * k;
-          if (e < np * NW) {
-            const int p = e / NW, rem = e % NW, r = rem / ST, l = rem % ST;
-            const int q = l + w - 1 - ((s_cw[p] >> (8 * r)) & 255);  // window index of cell s0 + l
-            dst[j] = p * SS + rem;
-            if (q >= 0 && q < w)
-              vals[j] = *reinterpret_cast<const T*>(
-                  pwb + (uint32_t)(s_map[p] * rs + r * w + q) * (uint32_t)sizeof(T));
-          }
-        } else if (k < NW + NG) {
-          const int e = t + kSubThreads * (k - NW);
-          if (e < np * NG) {
-            const int p = e / NG, c = e % NG;
-            dst[j] = p * SS + SW + c;
-            vals[j] = *reinterpret_cast<const T*>(
-                pwb + (uint32_t)(s_map[p] * rs + wko + c) * (uint32_t)sizeof(T));
+        for (int j = 0; j < kStageVec; ++j) {
+          const int e = e0 + t + kSubThreads * j;
+          if (e < nv) v[j] = pw4[(int64_t)s_map[e / R4] * R4 + e % R4];
+        }
+#pragma unroll
+        for (int j = 0; j < kStageVec; ++j) {
+          const int e = e0 + t + kSubThreads * j;
+          if (e >= nv) continue;
+          const int p = e / R4, c0 = (e % R4) * 4;
+          const int cw = s_cw[p];
+          const T xp = s_x[p];
+          int r = c0 / w, q = c0 - r * w;
+          const float vals[4] = {v[j].x, v[j].y, v[j].z, v[j].w};
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int c = c0 + u;
+            if (c < D * w) {
+              const int l = q + ((cw >> (8 * r)) & 255) - (w - 1);  // cell s0 + l along r
+              if (l >= 0 && l < ST) s_v[p * SS + r * ST + l] = r == 0 ? (T)vals[u] * xp : (T)vals[u];
+            } else if (c >= wko && c < wko + NG) {
+              s_v[p * SS + SW + c - wko] = (T)vals[u];
+            }
+            if (++q == w) {
+              q = 0;
+              ++r;
+            }
           }
         }
       }
+      __syncthreads();
+    } else {
+      __syncthreads();
+      if (t < np) {
+        const int2 ent = list[base + t];
+        s_map[t] = ent.x;
+        s_cw[t] = ent.y;
+      }
+      __syncthreads();
+      // x of the lane's own point, loaded with the staging loads
+      T xv = T(0);
+      if (t < np) xv = (T)x[s_map[t]];
+      // Items per lane: NW window items (e = p NW + r ST + l, e = t + 64 k) then
+      // NG weight items (e = p NG + c, e = t + 64 (k - NW)).  Offsets into pw
+      // are 32-bit (point sets whose rows exceed 4 GiB spread whole tiles).
+#pragma unroll 1
+      for (int k0 = 0; k0 < NW + NG; k0 += kStageChunk) {
+        T vals[kStageChunk];
+        int dst[kStageChunk];
 #pragma unroll
-      for (int j = 0; j < kStageChunk; ++j)
-        if (dst[j] >= 0) s_v[dst[j]] = vals[j];
+        for (int j = 0; j < kStageChunk; ++j) {
+          const int k = k0 + j;
+          vals[j] = T(0);
+          dst[j] = -1;
+          if (k < NW) {
+            const int e = t + kSubThreads * k;
+            if (e < np * NW) {
+              const int p = e / NW, rem = e % NW, r = rem / ST, l = rem % ST;
+              const int q = l + w - 1 - ((s_cw[p] >> (8 * r)) & 255);  // window index of cell s0 + l
+              dst[j] = p * SS + rem;
+              if (q >= 0 && q < w)
+                vals[j] = *reinterpret_cast<const T*>(
+                    pwb + (uint32_t)(s_map[p] * rs + r * w + q) * (uint32_t)sizeof(T));
+            }
+          } else if (k < NW + NG) {
+            const int e = t + kSubThreads * (k - NW);
+            if (e < np * NG) {
+              const int p = e / NG, c = e % NG;
+              dst[j] = p * SS + SW + c;
+              vals[j] = *reinterpret_cast<const T*>(
+                  pwb + (uint32_t)(s_map[p] * rs + wko + c) * (uint32_t)sizeof(T));
+            }
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < kStageChunk; ++j)
+          if (dst[j] >= 0) s_v[dst[j]] = vals[j];
+      }
+      __syncthreads();
+      // dimension-0 window values times x_i; padding entries all zero
+      if (t < np) {
+#pragma unroll
+        for (int l = 0; l < ST; ++l) s_v[t * SS + l] *= xv;
+      } else if (t < np4) {
+#pragma unroll
+        for (int c = 0; c < SS; ++c) s_v[t * SS + c] = T(0);
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    // dimension-0 window values times x_i; padding entries all zero
-    if (t < np) {
-#pragma unroll
-      for (int l = 0; l < ST; ++l) s_v[t * SS + l] *= xv;
-    } else if (t < np4) {
-#pragma unroll
-      for (int c = 0; c < SS; ++c) s_v[t * SS + c] = T(0);
-    }
-    __syncthreads();
     for (int p = 0; p < np4; p += 4) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -443,10 +503,9 @@ void exclusive_scan_counts(const int* in, int64_t n, int64_t* out, hipStream_t s
 
 void spread_sub_launch(Plan* P, const Records& R, const double* xs) {
   if (R.n_sub <= 0) throw Error{GP_EDEVICE, "internal: sub-tile lists missing"};
-  if (P->precision == GP_FP64)
-    launch_sub_t<double>(P, R, xs);
-  else
-    launch_sub_t<float>(P, R, xs);
+  if (P->precision != GP_FP32_BULK || (P->d == 2 && R.rs % 4 != 0))
+    throw Error{GP_EDEVICE, "internal: sub-tile spreading needs fp32 rows (padded to 16 bytes in 2-D)"};
+  launch_sub_t<float>(P, R, xs);
 }
 
 }  // namespace gp
