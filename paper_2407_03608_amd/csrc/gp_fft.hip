@@ -180,6 +180,34 @@ __device__ __forceinline__ int64_t elem_off(int i, int ips, int64_t es, int64_t 
   return (int64_t)(i >> ips) * es + (int64_t)(i & ((1 << ips) - 1)) * es1;
 }
 
+// Buffer-addressed element access (the default for passes without four-step
+// twiddles): a workgroup-uniform buffer resource at the lowest line start of
+// the workgroup, 32-bit byte offsets per element, and an offset past the
+// resource's range for elements outside the pruning window (the load returns
+// zero, the store is dropped), so the window tests cost no branches and the
+// addresses no 64-bit arithmetic.  The host enables it only where every offset
+// a workgroup forms fits below kBufRange.
+constexpr unsigned kBufRange = 0x7fffffffu;
+constexpr unsigned kBufOut = 0x80000000u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)kBufRange,
+                                           0x00020000);
+}
+__device__ __forceinline__ float2 buf_load(__amdgpu_buffer_rsrc_t r, unsigned off, float2*) {
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ double2 buf_load(__amdgpu_buffer_rsrc_t r, unsigned off, double2*) {
+  return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ void buf_store(float2 v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  using U = __attribute__((ext_vector_type(2))) unsigned;
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U, v), r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void buf_store(double2 v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  using U = __attribute__((ext_vector_type(4))) unsigned;
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U, v), r, (int)off, 0, 0);
+}
+
 struct KParams {
   int64_t ntrans, inner, in_os, out_os, in_es, in_cs, out_es, out_cs;
   int64_t in_cs1, in_es1, out_cs1, out_es1;
@@ -194,11 +222,11 @@ struct KParams {
 // X[j + m L/R], twiddle exp(s 2 pi i k m / (Ls R)) (one table load, powers by
 // recurrence), outputs Y[(j - k) R + k + q Ls].  Then either exchange through
 // LDS into the next stage's inputs or, on the last stage, store.
-template <typename T, typename V, int L, int EPT, int Ls>
+template <typename T, typename V, int L, int EPT, int Ls, bool BUF>
 __device__ __forceinline__ void stages(V (&v)[EPT], T* __restrict__ buf, int jt,
                                        const V* __restrict__ tw, int s, bool act, V* dst,
                                        int64_t dstride, const KParams& p, const V* tw4,
-                                       int64_t row4) {
+                                       int64_t row4, __amdgpu_buffer_rsrc_t orsrc, int odl) {
   constexpr int TPT = L / EPT;
   constexpr int R = next_radix(L / Ls, EPT);
   static_assert(R > 0, "unsupported FFT length");
@@ -245,10 +273,26 @@ __device__ __forceinline__ void stages(V (&v)[EPT], T* __restrict__ buf, int jt,
       }
       __syncthreads();
     }
-    stages<T, V, L, EPT, Ls * R>(v, buf, jt, tw, s, act, dst, dstride, p, tw4, row4);
+    stages<T, V, L, EPT, Ls * R, BUF>(v, buf, jt, tw, s, act, dst, dstride, p, tw4, row4, orsrc,
+                                      odl);
   } else {
     // last stage: k = j, outputs at j + q L/R
     if (!act) return;
+    if constexpr (BUF) {
+      const int pm = (1 << p.out_ips) - 1;
+      const int oes = (int)dstride, oes1 = (int)p.out_es1;
+      const int i0 = jt - p.out_start;
+#pragma unroll
+      for (int u = 0; u < NB; ++u)
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          int i = i0 + TPT * u + q * (L / R);
+          i = i < 0 ? i + L : i;
+          const int off = odl + (i >> p.out_ips) * oes + (i & pm) * oes1;
+          buf_store(v[u * R + q], orsrc, i < p.n_out ? (unsigned)off * (unsigned)sizeof(V) : kBufOut);
+        }
+      return;
+    }
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
       const int j = jt + TPT * u;
@@ -271,7 +315,7 @@ __device__ __forceinline__ void stages(V (&v)[EPT], T* __restrict__ buf, int jt,
   }
 }
 
-template <typename T, int L, int EPT, int B>
+template <typename T, int L, int EPT, int B, bool BUF>
 __global__ __launch_bounds__(B*(L / EPT)) void fft_pass_kernel(
     const typename V2<T>::type* __restrict__ in, typename V2<T>::type* __restrict__ out,
     const typename V2<T>::type* __restrict__ tw, const typename V2<T>::type* __restrict__ tw4,
@@ -306,6 +350,33 @@ __global__ __launch_bounds__(B*(L / EPT)) void fft_pass_kernel(
   constexpr int R1 = next_radix(L, EPT);
   constexpr int NB1 = EPT / R1;
   V v[EPT];
+  __amdgpu_buffer_rsrc_t orsrc = buf_rsrc(out);
+  int odl = 0;
+  if constexpr (BUF) {
+    // line starts are non-decreasing in the transform index (checked on the
+    // host), so the workgroup's first line is its lowest
+    const int64_t t0 = bid * B;
+    const int64_t o0 = t0 / p.inner, c0 = t0 - o0 * p.inner;
+    const V* ib = in + o0 * p.in_os + (c0 >> p.in_cps) * p.in_cs + (c0 & ((1 << p.in_cps) - 1)) * p.in_cs1;
+    V* ob = out + o0 * p.out_os + (c0 >> p.out_cps) * p.out_cs + (c0 & ((1 << p.out_cps) - 1)) * p.out_cs1;
+    const __amdgpu_buffer_rsrc_t irsrc = buf_rsrc(ib);
+    orsrc = buf_rsrc(ob);
+    const int idl = (int)(src - ib);
+    odl = (int)(dst - ob);
+    const int pm = (1 << p.in_ips) - 1;
+    const int ies = (int)p.in_es, ies1 = (int)p.in_es1;
+    const int i0 = jt - p.in_start;
+#pragma unroll
+    for (int u = 0; u < NB1; ++u)
+#pragma unroll
+      for (int m = 0; m < R1; ++m) {
+        int i = i0 + TPT * u + m * (L / R1);
+        i = i < 0 ? i + L : i;
+        const int off = idl + (i >> p.in_ips) * ies + (i & pm) * ies1;
+        v[u * R1 + m] = buf_load(irsrc, act && i < p.n_in ? (unsigned)off * (unsigned)sizeof(V) : kBufOut,
+                                 (V*)nullptr);
+      }
+  } else
 #pragma unroll
   for (int u = 0; u < NB1; ++u) {
     const int j = jt + TPT * u;
@@ -326,7 +397,8 @@ __global__ __launch_bounds__(B*(L / EPT)) void fft_pass_kernel(
       v[u * R1 + m] = val;
     }
   }
-  stages<T, V, L, EPT, 1>(v, buf + b * LP, jt, tw, p.sign, act, dst, p.out_es, p, tw4, row4);
+  stages<T, V, L, EPT, 1, BUF>(v, buf + b * LP, jt, tw, p.sign, act, dst, p.out_es, p, tw4, row4,
+                               orsrc, odl);
 }
 
 constexpr int ept_for(int L) { return (L % 3 == 0) ? (L < 24 ? L : 24) : (L < 32 ? L : 32); }
@@ -337,6 +409,45 @@ constexpr int batch_for(int L, int elem_bytes) {
   int cap = (80 * 1024) / ((L + L / 32) * elem_bytes);
   if (cap < 1) cap = 1;
   return b < cap ? b : cap;
+}
+
+// Whether workgroups of B consecutive transforms can use buffer addressing:
+// no four-step twiddles, non-negative strides, line starts non-decreasing in
+// the transform index (so a workgroup's first line is its lowest), and every
+// byte offset from a workgroup's first line below kBufRange.
+bool buf_fits(const KParams& p, const FftPass& q, int B, int64_t vb) {
+  if (q.tw4 != nullptr) return false;
+  auto side = [&](int64_t os, int64_t cs, int64_t cs1, int cps, int64_t es, int64_t es1, int ips,
+                  int n) {
+    if (os < 0 || cs < 0 || cs1 < 0 || es < 0 || es1 < 0) return false;
+    int64_t step = os;  // largest start difference of consecutive transforms
+    if (p.inner > 1) {
+      if (cps && cs1 > cs) return false;
+      const int64_t cmax = ((p.inner - 1) >> cps) * cs + (cps ? cs1 : 0);
+      if (os < cmax && p.ntrans > p.inner) return false;
+      step = std::max(os, cs);
+    }
+    const int64_t emax = n > 0 ? ((int64_t)(n - 1) >> ips) * es + (ips ? es1 : 0) : 0;
+    return ((int64_t)(B - 1) * step + emax + 1) * vb < (int64_t)kBufRange - 64;
+  };
+  return side(p.in_os, p.in_cs, p.in_cs1, p.in_cps, p.in_es, p.in_es1, p.in_ips, p.n_in) &&
+         side(p.out_os, p.out_cs, p.out_cs1, p.out_cps, p.out_es, p.out_es1, p.out_ips, p.n_out);
+}
+
+template <typename T, int L, int EPT, int B>
+void launch_kernel(bool buf, int64_t nblk, const KParams& p, const void* in, void* out,
+                   const void* tw, const void* tw4, hipStream_t s) {
+  using V = typename V2<T>::type;
+  if (nblk <= 0) return;
+  if (buf)
+    hipLaunchKernelGGL((fft_pass_kernel<T, L, EPT, B, true>), dim3((unsigned)nblk), dim3(B * (L / EPT)),
+                       0, s, static_cast<const V*>(in), static_cast<V*>(out),
+                       static_cast<const V*>(tw), static_cast<const V*>(tw4), p);
+  else
+    hipLaunchKernelGGL((fft_pass_kernel<T, L, EPT, B, false>), dim3((unsigned)nblk), dim3(B * (L / EPT)),
+                       0, s, static_cast<const V*>(in), static_cast<V*>(out),
+                       static_cast<const V*>(tw), static_cast<const V*>(tw4), p);
+  GP_CHECK_LAUNCH();
 }
 
 template <typename T, int L>
@@ -376,23 +487,15 @@ void launch_len(const FftPass& q, const void* in, void* out, const void* tw, hip
   // contiguous bytes; the column passes are bound by cache-line requests per
   // byte, and this wins (0.81 -> 0.72 ms) even though the 128-VGPR budget of a
   // 1024-thread workgroup spills a few registers.
+  const int64_t vb = (int64_t)sizeof(V);
   if constexpr (L == 8192) {
     if constexpr (sizeof(T) == 4) {
       if (q.inner > 1) {
-        const int64_t nb4 = (p.ntrans + 3) / 4;
-        if (nb4 <= 0) return;
-        hipLaunchKernelGGL((fft_pass_kernel<T, L, 32, 4>), dim3((unsigned)nb4), dim3(4 * (L / 32)),
-                           0, s, static_cast<const V*>(in), static_cast<V*>(out),
-                           static_cast<const V*>(tw), static_cast<const V*>(q.tw4), p);
-        GP_CHECK_LAUNCH();
+        launch_kernel<T, L, 32, 4>(buf_fits(p, q, 4, vb), (p.ntrans + 3) / 4, p, in, out, tw, q.tw4, s);
         return;
       }
     }
-    if (p.ntrans <= 0) return;
-    hipLaunchKernelGGL((fft_pass_kernel<T, L, 16, 1>), dim3((unsigned)p.ntrans), dim3(L / 16),
-                       0, s, static_cast<const V*>(in), static_cast<V*>(out),
-                       static_cast<const V*>(tw), static_cast<const V*>(q.tw4), p);
-    GP_CHECK_LAUNCH();
+    launch_kernel<T, L, 16, 1>(buf_fits(p, q, 1, vb), p.ntrans, p, in, out, tw, q.tw4, s);
   } else {
     // Long strided (column) fp32 transforms: two columns per workgroup, so
     // pairs of adjacent lanes read adjacent elements of one cache line.  fp64
@@ -400,21 +503,11 @@ void launch_len(const FftPass& q, const void* in, void* out, const void* tw, hip
     // the forward column pass at d=2 N=1e6 with contiguous output).
     if constexpr (B == 1 && L >= 6144) {
       if (q.inner > 1 && sizeof(T) == 4) {
-        const int64_t nb2 = (p.ntrans + 1) / 2;
-        if (nb2 <= 0) return;
-        hipLaunchKernelGGL((fft_pass_kernel<T, L, EPT, 2>), dim3((unsigned)nb2), dim3(2 * (L / EPT)),
-                           0, s, static_cast<const V*>(in), static_cast<V*>(out),
-                           static_cast<const V*>(tw), static_cast<const V*>(q.tw4), p);
-        GP_CHECK_LAUNCH();
+        launch_kernel<T, L, EPT, 2>(buf_fits(p, q, 2, vb), (p.ntrans + 1) / 2, p, in, out, tw, q.tw4, s);
         return;
       }
     }
-    const int64_t nblk = (p.ntrans + B - 1) / B;
-    if (nblk <= 0) return;
-    hipLaunchKernelGGL((fft_pass_kernel<T, L, EPT, B>), dim3((unsigned)nblk), dim3(B * (L / EPT)),
-                       0, s, static_cast<const V*>(in), static_cast<V*>(out),
-                       static_cast<const V*>(tw), static_cast<const V*>(q.tw4), p);
-    GP_CHECK_LAUNCH();
+    launch_kernel<T, L, EPT, B>(buf_fits(p, q, B, vb), (p.ntrans + B - 1) / B, p, in, out, tw, q.tw4, s);
   }
 }
 

@@ -116,6 +116,11 @@ struct Records {
 
 // ------------------------------------------------------------------- plan --
 // A plan: its numbers (PlanRules, chosen on the host) and its device data.
+// Step-3 tile of orthant points in 2-D: the mode kernels visit these tiles in
+// order of their distance from the origin, so the points in flight at any time
+// lie in one annulus and share a narrow band of the radial table.
+constexpr int kModeTileX = 64, kModeTileY = 4;
+
 struct Plan : PlanRules {
   int64_t n = 0;
   double eta = 0;
@@ -136,6 +141,9 @@ struct Plan : PlanRules {
   int interp_mode = 0;        // 0 default, 1 cache gather, 2 per-bin LDS tiles
   DevBuf atab;                // T [a_rows][nkp(nkp+1)/2] upper triangle of A_k'k(|n|^2)
   DevBuf rowidx;              // int32 [d M^2 + 1]: |n|^2 -> row (d >= 2)
+  DevBuf mode_tiles;          // int32: 2-D orthant tiles of kModeTileX x kModeTileY points,
+                              // nearest the origin first (step3 = 0)
+  int64_t mode_ntx = 0;       // tiles along n_0
   DevBuf dec;                 // T [d][M+1] 1/psi^(2 pi n / nf_r)
   DevBuf tw[3];               // FFT twiddles per distinct length (T complex)
   DevBuf tw4;                 // four-step twiddles (1-D, T complex, length nf)

@@ -122,7 +122,10 @@ struct RadialArgs {
   int64_t nf, L1, L2;
   int nsets;              // vector sets (consecutive, set_stride elements apart)
   int64_t set_stride;
+  const int* tiles;       // 2-D: the block -> orthant tile order (null: linear in q)
+  int64_t ntx;            // tiles along n_0
 };
+static_assert(kModeTileX * kModeTileY == kThreads, "one orthant tile per block");
 
 __device__ __forceinline__ int64_t radial_store(const RadialArgs& a, const int64_t* nv) {
   if (!a.fourstep) {
@@ -144,11 +147,16 @@ __global__ __launch_bounds__(kThreads) void mode_radial_kernel(
     const int* __restrict__ rowidx, const T* __restrict__ dec) {
   using V = typename V2<T>::type;
   constexpr int NP = NK * (NK + 1) / 2;
-  const int64_t tid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (tid >= a.Q) return;
   const int64_t M1 = a.M + 1;
   int64_t an[3] = {0, 0, 0};
-  {
+  if (a.tiles) {
+    const int64_t t = a.tiles[blockIdx.x];
+    an[0] = (t % a.ntx) * kModeTileX + threadIdx.x % kModeTileX;
+    an[1] = (t / a.ntx) * kModeTileY + threadIdx.x / kModeTileX;
+    if (an[0] > a.M || an[1] > a.M) return;
+  } else {
+    const int64_t tid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (tid >= a.Q) return;
     int64_t q = tid;
     for (int r = 0; r < a.d; ++r) {
       an[r] = q % M1;
@@ -243,19 +251,28 @@ __global__ __launch_bounds__(kThreads) void mode_radial_kernel(
 // d = 2: one thread per (orthant point, sign pattern), the two patterns of a
 // point on adjacent lanes, so each reads the same row of A in the same load
 // instruction (one fetch) while holding half the registers of a thread that
-// owns both patterns.
+// owns both patterns.  Two blocks per orthant tile (two of its rows each).
 template <typename T, int NK>
 __global__ __launch_bounds__(kThreads) void mode_radial2_kernel(
     RadialArgs a, typename V2<T>::type* __restrict__ C, const T* __restrict__ Atab,
     const int* __restrict__ rowidx, const T* __restrict__ dec) {
   using V = typename V2<T>::type;
   constexpr int NP = NK * (NK + 1) / 2;
-  const int64_t tid = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  const int64_t q = tid >> 1;
-  const int h = (int)(tid & 1);
-  if (q >= a.Q) return;
+  const int h = (int)(threadIdx.x & 1);
+  const int lp = (int)(threadIdx.x >> 1);
   const int64_t M1 = a.M + 1;
-  const int64_t an0 = q % M1, an1 = q / M1;
+  int64_t an0, an1;
+  if (a.tiles) {
+    const int64_t t = a.tiles[blockIdx.x >> 1];
+    an0 = (t % a.ntx) * kModeTileX + lp % kModeTileX;
+    an1 = (t / a.ntx) * kModeTileY + (kModeTileY / 2) * (blockIdx.x & 1) + lp / kModeTileX;
+    if (an0 > a.M || an1 > a.M) return;
+  } else {
+    const int64_t q = ((int64_t)blockIdx.x * kThreads + threadIdx.x) >> 1;
+    if (q >= a.Q) return;
+    an0 = q % M1;
+    an1 = q / M1;
+  }
   const T* Ar = Atab + (int64_t)rowidx[an0 * an0 + an1 * an1] * NP;
   const T D = dec[an0] * dec[M1 + an1];
   // pattern 1 negates n_1; it repeats pattern 0 when n_0 = 0 or n_1 = 0
@@ -523,6 +540,8 @@ void launch_radial_nk(Plan* P) {
   a.pair_stride = P->fourstep ? P->nf[0] : F;
   a.nsets = P->gv.nsets;
   a.set_stride = P->npair * a.pair_stride;
+  a.tiles = nullptr;
+  a.ntx = 0;
   auto* C = static_cast<typename V2<T>::type*>(P->gv.C);
   if (P->step3 == 2) {
     hipLaunchKernelGGL((mode_lowrank_kernel<T, NK>), dim3((unsigned)((a.Q + kThreads - 1) / kThreads)),
@@ -543,14 +562,22 @@ void launch_radial_nk(Plan* P) {
   }
   // fp64: 1.52 -> 1.43 ms at d=2 N=1e6; fp32 unchanged (0.37 ms), kept on
   // the two-pattern kernel
+  // 2-D: orthant tiles nearest the origin first (the table rows in use then
+  // form a band that stays in the caches)
+  int64_t nblk = (a.Q + kThreads - 1) / kThreads;
+  if (P->d == 2 && P->mode_tiles.p) {
+    a.tiles = P->mode_tiles.as<int>();
+    a.ntx = P->mode_ntx;
+    nblk = P->mode_ntx * (P->M / kModeTileY + 1);
+  }
   if (P->d == 2 && !a.fourstep && sizeof(T) == 8) {
-    hipLaunchKernelGGL((mode_radial2_kernel<T, NK>), dim3((unsigned)((2 * a.Q + kThreads - 1) / kThreads)),
+    hipLaunchKernelGGL((mode_radial2_kernel<T, NK>), dim3((unsigned)(a.tiles ? 2 * nblk : (2 * a.Q + kThreads - 1) / kThreads)),
                        dim3(kThreads), 0, P->stream, a, C, P->atab.as<T>(), P->rowidx.as<int>(),
                        P->dec.as<T>());
     GP_CHECK_LAUNCH();
     return;
   }
-  hipLaunchKernelGGL((mode_radial_kernel<T, NK>), dim3((unsigned)((a.Q + kThreads - 1) / kThreads)),
+  hipLaunchKernelGGL((mode_radial_kernel<T, NK>), dim3((unsigned)nblk),
                      dim3(kThreads), 0, P->stream, a, C,
                      P->atab.as<T>(), P->d > 1 ? P->rowidx.as<int>() : nullptr, P->dec.as<T>());
   GP_CHECK_LAUNCH();

@@ -80,7 +80,7 @@ void retag_plan_stream(Plan* P, hipStream_t st) {
   Records& R = P->rec;
   DevBuf* bufs[] = {&R.perm, &R.cell, &R.pw, &R.bin_start, &R.sp_work, &R.sp_red, &R.in_work,
                     &R.in_work2, &R.part, &R.sub_off, &R.sub_list, &P->nodes_d, &P->bary_d,
-                    &P->gtab, &P->etab, &P->vtd, &P->lr_off, &P->atab, &P->rowidx, &P->dec,
+                    &P->gtab, &P->etab, &P->vtd, &P->lr_off, &P->atab, &P->rowidx, &P->mode_tiles, &P->dec,
                     &P->tw[0], &P->tw[1], &P->tw[2], &P->tw4, &P->gridA, &P->gridB, &P->gridB2,
                     &P->gridC, &P->mA, &P->mB, &P->mB2, &P->mC, &P->vec, &P->cg_part, &P->cg_S};
   for (DevBuf* b : bufs)
@@ -638,7 +638,8 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
   bytes += spread_list_bound_bytes(P, n);
   if (P->step3 != 1)  // the low-rank rows (step3 = 2) hold at most the full row's size
     bytes += (size_t)P->a_rows * (P->nkp * (P->nkp + 1) / 2) * ts + rowmap.size() * sizeof(int) +
-             (P->step3 == 2 ? (size_t)(P->a_rows + 1) * sizeof(int64_t) : 0);
+             (P->step3 == 2 ? (size_t)(P->a_rows + 1) * sizeof(int64_t) : 0) +
+             (d == 2 ? (size_t)(P->M / kModeTileX + 1) * (P->M / kModeTileY + 1) * sizeof(int) : 0);
   else
     bytes += (size_t)P->nt_eff * P->nk * (P->M + 1) * ts * 2;
   bytes += (size_t)n * 8 * sizeof(double) + (kCgBlocks + kCgScalars) * sizeof(double);  // vectors
@@ -720,6 +721,24 @@ int build_plan(int d, int64_t n, const double* pts, const double* sigma, const d
     if (d > 1) {
       P->rowidx.alloc(rowmap.size() * sizeof(int), P->stream);
       GP_HIP(hipMemcpyAsync(P->rowidx.p, rowmap.data(), rowmap.size() * sizeof(int),
+                            hipMemcpyHostToDevice, s));
+    }
+    std::vector<int> order;  // read by the copy below until the stream is synchronised
+    if (d == 2 && P->step3 == 0 && !P->fourstep) {
+      // tiles of the orthant {0..M}^2 by the distance of their corner nearest the
+      // origin (stable), so the rows of the table in use at any time form a band
+      const int64_t ntx = P->M / kModeTileX + 1, nty = P->M / kModeTileY + 1;
+      order.resize((size_t)(ntx * nty));
+      std::vector<int64_t> key(order.size());
+      for (int64_t t = 0; t < ntx * nty; ++t) {
+        const int64_t x0 = (t % ntx) * kModeTileX, y0 = (t / ntx) * kModeTileY;
+        order[(size_t)t] = (int)t;
+        key[(size_t)t] = x0 * x0 + y0 * y0;
+      }
+      std::stable_sort(order.begin(), order.end(), [&](int u, int v) { return key[u] < key[v]; });
+      P->mode_ntx = ntx;
+      P->mode_tiles.alloc(order.size() * sizeof(int), P->stream);
+      GP_HIP(hipMemcpyAsync(P->mode_tiles.p, order.data(), order.size() * sizeof(int),
                             hipMemcpyHostToDevice, s));
     }
     GP_HIP(hipStreamSynchronize(s));
