@@ -262,12 +262,17 @@ __device__ __forceinline__ void stages(V (&v)[EPT], T* __restrict__ buf, int jt,
         for (int q = 0; q < R; ++q) buf[lpad((j - k) * R + k + q * Ls)] = comp ? v[u * R + q].y : v[u * R + q].x;
       }
       __syncthreads();
+      // the read index is jt plus a compile-time c; where c is a multiple of
+      // 32, lpad(jt + c) = lpad(jt) + c + c/32, an immediate offset
+      const int rb = lpad(jt);
 #pragma unroll
       for (int u = 0; u < NB2; ++u) {
         const int j = jt + TPT * u;
 #pragma unroll
         for (int m = 0; m < R2; ++m) {
-          const T val = buf[lpad(j + m * (L / R2))];
+          const int c = TPT * u + m * (L / R2);
+          const T val = (TPT % 32 == 0 && (L / R2) % 32 == 0) ? buf[rb + c + (c >> 5)]
+                                                             : buf[lpad(j + m * (L / R2))];
           if (comp) v[u * R2 + m].y = val; else v[u * R2 + m].x = val;
         }
       }
@@ -315,8 +320,23 @@ __device__ __forceinline__ void stages(V (&v)[EPT], T* __restrict__ buf, int jt,
   }
 }
 
-template <typename T, int L, int EPT, int B, bool BUF>
-__global__ __launch_bounds__(B*(L / EPT)) void fft_pass_kernel(
+// Waves per SIMD that the LDS buffer allows (160 KB per CU, four SIMDs),
+// passed to the compiler as its register budget for the long transforms:
+// more registers than that occupancy leaves would keep LDS idle.  Capped
+// where the elements held per thread need more registers than the budget.
+constexpr int fft_waves(int L, int EPT, int B, int tb) {
+  if (L < 1536) return 1;
+  const int lds = B * (L + L / 32) * tb;
+  const int wgs = (160 * 1024) / lds;
+  const int w = wgs * ((B * (L / EPT) + 63) / 64) / 4;
+  const int need = EPT * 2 * tb / 4 + 48;  // registers of the elements and the temporaries
+  const int wr = 512 / need;
+  const int m = w < wr ? w : wr;
+  return m < 1 ? 1 : (m > 8 ? 8 : m);
+}
+
+template <typename T, int L, int EPT, int B, bool BUF, int S>
+__global__ __launch_bounds__(B*(L / EPT), fft_waves(L, EPT, B, (int)sizeof(T))) void fft_pass_kernel(
     const typename V2<T>::type* __restrict__ in, typename V2<T>::type* __restrict__ out,
     const typename V2<T>::type* __restrict__ tw, const typename V2<T>::type* __restrict__ tw4,
     KParams p) {
@@ -390,14 +410,14 @@ __global__ __launch_bounds__(B*(L / EPT)) void fft_pass_kernel(
         val = src[elem_off(i, p.in_ips, p.in_es, p.in_es1)];
         if (tw4 != nullptr && p.tw4_at_load) {
           V wv = tw4[((int64_t)pos * row4) % p.L4];
-          if (p.sign > 0) wv.y = -wv.y;
+          if (S > 0) wv.y = -wv.y;
           val = cmul(val, wv);
         }
       }
       v[u * R1 + m] = val;
     }
   }
-  stages<T, V, L, EPT, 1, BUF>(v, buf + b * LP, jt, tw, p.sign, act, dst, p.out_es, p, tw4, row4,
+  stages<T, V, L, EPT, 1, BUF>(v, buf + b * LP, jt, tw, S, act, dst, p.out_es, p, tw4, row4,
                                orsrc, odl);
 }
 
@@ -439,14 +459,17 @@ void launch_kernel(bool buf, int64_t nblk, const KParams& p, const void* in, voi
                    const void* tw, const void* tw4, hipStream_t s) {
   using V = typename V2<T>::type;
   if (nblk <= 0) return;
-  if (buf)
-    hipLaunchKernelGGL((fft_pass_kernel<T, L, EPT, B, true>), dim3((unsigned)nblk), dim3(B * (L / EPT)),
-                       0, s, static_cast<const V*>(in), static_cast<V*>(out),
-                       static_cast<const V*>(tw), static_cast<const V*>(tw4), p);
+  const dim3 g((unsigned)nblk), t(B * (L / EPT));
+  const V *i = static_cast<const V*>(in), *w = static_cast<const V*>(tw), *w4 = static_cast<const V*>(tw4);
+  V* o = static_cast<V*>(out);
+  if (buf && p.sign < 0)
+    hipLaunchKernelGGL((fft_pass_kernel<T, L, EPT, B, true, -1>), g, t, 0, s, i, o, w, w4, p);
+  else if (buf)
+    hipLaunchKernelGGL((fft_pass_kernel<T, L, EPT, B, true, 1>), g, t, 0, s, i, o, w, w4, p);
+  else if (p.sign < 0)
+    hipLaunchKernelGGL((fft_pass_kernel<T, L, EPT, B, false, -1>), g, t, 0, s, i, o, w, w4, p);
   else
-    hipLaunchKernelGGL((fft_pass_kernel<T, L, EPT, B, false>), dim3((unsigned)nblk), dim3(B * (L / EPT)),
-                       0, s, static_cast<const V*>(in), static_cast<V*>(out),
-                       static_cast<const V*>(tw), static_cast<const V*>(tw4), p);
+    hipLaunchKernelGGL((fft_pass_kernel<T, L, EPT, B, false, 1>), g, t, 0, s, i, o, w, w4, p);
   GP_CHECK_LAUNCH();
 }
 
