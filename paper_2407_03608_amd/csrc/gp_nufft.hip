@@ -580,7 +580,8 @@ template <typename T, bool PIPE, int D, int W>
 __global__ __launch_bounds__(kThreads) void interp_super_kernel(
     NuArgs a, const typename V2<T>::type* __restrict__ grid, const int* __restrict__ cell,
     const T* __restrict__ pw, int rs, const int* __restrict__ bin_start,
-    const int4* __restrict__ work, const double* __restrict__ x, double* __restrict__ y) {
+    const int4* __restrict__ work, const double* __restrict__ x, double* __restrict__ y,
+    int64_t nwork, int grp) {
   using V = typename V2<T>::type;
   constexpr int PB = kPB2<D, T>;
   constexpr int NI = (PB * kRG + kThreads - 1) / kThreads;  // items per thread
@@ -596,7 +597,15 @@ __global__ __launch_bounds__(kThreads) void interp_super_kernel(
   int* s_cell = reinterpret_cast<int*>(s_rec + PB * ls);           // [PB][D]
   int* s_idx = s_cell + D * PB;                                     // [PB] sorted index
 
-  const int4 wk = work[blockIdx.x];
+  // block -> work item: groups of grp consecutive items per XCD (blocks go to
+  // the XCDs round-robin); the grid is padded to a multiple of 8 grp
+  int64_t item = blockIdx.x;
+  if (grp > 0) {
+    const int64_t xx = item % 8, k = item / 8;
+    item = ((k / grp) * 8 + xx) * grp + k % grp;
+    if (item >= nwork) return;
+  }
+  const int4 wk = work[item];
   const int nsb0 = (a.nbins[0] + 1) / 2, nsb1 = (a.nbins[1] + 1) / 2;
   const int sx = wk.x % nsb0, sy = (wk.x / nsb0) % nsb1, sz = D > 2 ? wk.x / (nsb0 * nsb1) : 0;
   const int t00 = sx * st0, t01 = sy * st1, t02 = sz * st2;
@@ -949,10 +958,16 @@ void launch_interp_super(Plan* P, const Records& R, const double* xs, double* ys
                                    : pick(interp_super_kernel<T, true, 2, 0>, interp_super_kernel<T, true, 3, 0>))
                    : pick(interp_super_kernel<T, false, 2, 0>, interp_super_kernel<T, false, 3, 0>);
   if (interp_super_smem<T>(P, R.rs) > kSmemCap) allow_big_lds(kern);
-  hipLaunchKernelGGL(kern, dim3((unsigned)R.n_in_work2), dim3(kThreads),
+  // work items (2x2 bin blocks in raster order) are dealt to the 8 XCDs in
+  // groups of 16 consecutive ones, so neighbouring blocks, whose halos
+  // overlap, read them through one L2 (d=3 N=1e7: 3.50 -> 3.20 ms)
+  constexpr int grp = 16;
+  const int64_t nw = R.n_in_work2;
+  const int64_t nblk = grp > 0 ? (nw + 8 * grp - 1) / (8 * grp) * (8 * grp) : nw;
+  hipLaunchKernelGGL(kern, dim3((unsigned)nblk), dim3(kThreads),
                      interp_super_smem<T>(P, R.rs), P->stream, a,
                      cur_gridA<typename V2<T>::type>(P), R.cell.as<int>(), R.pw.as<T>(), R.rs,
-                     R.bin_start.as<int>(), R.in_work2.as<int4>(), xs, ys);
+                     R.bin_start.as<int>(), R.in_work2.as<int4>(), xs, ys, nw, grp);
   GP_CHECK_LAUNCH();
 }
 
