@@ -440,15 +440,19 @@ bool buf_fits(const KParams& p, const FftPass& q, int B, int64_t vb) {
   auto side = [&](int64_t os, int64_t cs, int64_t cs1, int cps, int64_t es, int64_t es1, int ips,
                   int n) {
     if (os < 0 || cs < 0 || cs1 < 0 || es < 0 || es1 < 0) return false;
-    int64_t step = os;  // largest start difference of consecutive transforms
+    // largest start difference between the first and the last of B
+    // consecutive transforms: k steps to the next outer index (each at most
+    // os) and at most B - 1 steps within one (each at most cs)
+    int64_t span = (int64_t)(B - 1) * os;
     if (p.inner > 1) {
       if (cps && cs1 > cs) return false;
       const int64_t cmax = ((p.inner - 1) >> cps) * cs + (cps ? cs1 : 0);
       if (os < cmax && p.ntrans > p.inner) return false;
-      step = std::max(os, cs);
+      const int64_t k = (B - 1 + p.inner - 1) / p.inner;
+      span = k * os + (int64_t)(B - 1) * cs;
     }
     const int64_t emax = n > 0 ? ((int64_t)(n - 1) >> ips) * es + (ips ? es1 : 0) : 0;
-    return ((int64_t)(B - 1) * step + emax + 1) * vb < (int64_t)kBufRange - 64;
+    return (span + emax + 1) * vb < (int64_t)kBufRange - 64;
   };
   return side(p.in_os, p.in_cs, p.in_cs1, p.in_cps, p.in_es, p.in_es1, p.in_ips, p.n_in) &&
          side(p.out_os, p.out_cs, p.out_cs1, p.out_cps, p.out_es, p.out_es1, p.out_ips, p.n_out);
