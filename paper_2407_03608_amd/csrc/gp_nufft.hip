@@ -563,14 +563,14 @@ __global__ __launch_bounds__(kThreads) void interp_kernel(
 // order of every sum is fixed.  The next pair's tile is loaded into registers
 // while the current pair is computed (the kernel is otherwise latency-bound:
 // 1.71 -> 0.88 ms at d=2 N=1e6 fp64 on the 8192^2 grid).
-// Points staged per batch: 128 for fp32 grids in 2-D; 320 for fp32 grids in
-// 3-D, whose 2x2x1 block (20 x 20 x 12 cells at w = 5) is then staged once per
-// 320 points instead of per 128 (the block and the rows still fit 80 KB); 64
-// for fp64 grids, whose rows of 38 doubles per point would otherwise hold two
-// workgroups per CU (d=2 N=1e6: three workgroups per CU, the block staged about
-// twice as often, 0.79 -> 0.70 ms).
+// Points staged per batch: 128 for fp32 grids (in 3-D the 2x2x1 block of
+// 20 x 20 x 12 cells at w = 5 and the rows then take 49 KB, three workgroups
+// per CU: d=3 N=1e7 3.19 -> 2.71 ms against 320 points per batch at 80 KB,
+// although the block is staged more often); 64 for fp64 grids, whose rows of
+// 38 doubles per point would otherwise hold two workgroups per CU (d=2 N=1e6:
+// three, with the block staged about twice as often, 0.79 -> 0.70 ms).
 template <int D, typename T>
-constexpr int kPB2 = (D > 2 && sizeof(T) == 4) ? 320 : (sizeof(T) == 8 ? 64 : 128);
+constexpr int kPB2 = sizeof(T) == 8 ? 64 : 128;
 
 // tile cells per thread kept in flight by the pipelined variant (a d=3 block
 // of 2x2x1 bins of 8^3 cells with w = 5 has 20 x 20 x 12 = 4800 cells)
